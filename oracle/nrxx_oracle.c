@@ -1,0 +1,855 @@
+/*
+ * nrxx_oracle.c -- FP64 CPU reference for the NRxx steady-state solver of
+ * Hu & Li (arXiv 2206.13164): Hermite moment discretisation with Grad's local
+ * basis (Sec. 2.2), finite-volume operator R_ij (Sec. 2.3, eq. (13)-(15)),
+ * fast sweeping (Sec. 3.1, Alg. 1) and the FAS V-cycle (Sec. 3.2, Alg. 2).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Plain and slow on purpose: every function does
+ * the steps of the method in the order the paper states them, with no
+ * blocking or fusion.  Where the paper defers a detail to its references the
+ * reading used here is stated at the function.  It shares no code with the
+ * GPU library; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark may load it.
+ *
+ * Parity pins (tests/test_oracle_*.py): basis change, xi-multiplication,
+ * normalisation, macroscopic relations, Shakhov equilibrium and the
+ * regularisation term against Gauss-Hermite quadrature; the wall half-range
+ * integrals against adaptive quadrature; C_{M+1} against the Hermite roots;
+ * operator invariants (Maxwellian fixed point, mass conservation, mirror and
+ * transpose equivariance); serial == wavefront sweep; FS == explicit Euler
+ * steady state.  The exact flux/boundary/norm choices of the paper's own code
+ * are not printed in the paper: "parity unpinned" against the paper's
+ * numbers, pinned only by the invariants above.
+ */
+#include "nrxx_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define MMAX 24
+
+/* ------------------------------------------------------------------ */
+/* Index set {alpha in N^3 : |alpha| <= M} in graded order (Sec. 2.2). */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int M, N;
+  int *a;   /* N x 3 */
+  int *pos; /* (M+1)^3 table, -1 outside the set */
+} idxset;
+
+static idxset g_idx[MMAX + 1];
+
+static const idxset *idx_of(int M) {
+  idxset *s = &g_idx[M];
+  if (s->a) return s;
+  int N = (M + 1) * (M + 2) * (M + 3) / 6;
+  int *a = (int *)malloc(sizeof(int) * 3 * N);
+  int *pos = (int *)malloc(sizeof(int) * (M + 1) * (M + 1) * (M + 1));
+  for (int t = 0; t < (M + 1) * (M + 1) * (M + 1); ++t) pos[t] = -1;
+  int k = 0;
+  for (int n = 0; n <= M; ++n)
+    for (int a1 = n; a1 >= 0; --a1)
+      for (int a2 = n - a1; a2 >= 0; --a2) {
+        int a3 = n - a1 - a2;
+        a[3 * k] = a1; a[3 * k + 1] = a2; a[3 * k + 2] = a3;
+        pos[(a1 * (M + 1) + a2) * (M + 1) + a3] = k;
+        ++k;
+      }
+  s->M = M; s->N = N; s->pos = pos;
+  s->a = a; /* published last */
+  return s;
+}
+
+static int P3(const idxset *s, int a1, int a2, int a3) {
+  if (a1 < 0 || a2 < 0 || a3 < 0 || a1 + a2 + a3 > s->M) return -1;
+  return s->pos[(a1 * (s->M + 1) + a2) * (s->M + 1) + a3];
+}
+
+/* index of alpha + k e_d (k may be negative), -1 outside the set */
+static int shifted(const idxset *s, int alpha, int d, int k) {
+  int b[3] = {s->a[3 * alpha], s->a[3 * alpha + 1], s->a[3 * alpha + 2]};
+  b[d] += k;
+  return P3(s, b[0], b[1], b[2]);
+}
+
+static int deg(const idxset *s, int alpha) {
+  return s->a[3 * alpha] + s->a[3 * alpha + 1] + s->a[3 * alpha + 2];
+}
+
+int orc_nalpha(int M) { return (M + 1) * (M + 2) * (M + 3) / 6; }
+
+void orc_alpha_list(int M, int *out) {
+  const idxset *s = idx_of(M);
+  memcpy(out, s->a, sizeof(int) * 3 * s->N);
+}
+
+static double factorial(int n) {
+  double r = 1.0;
+  for (int k = 2; k <= n; ++k) r *= k;
+  return r;
+}
+
+/* Probabilists' Hermite polynomial He_n(x) by its three-term recurrence. */
+static double hermite(int n, double x) {
+  if (n == 0) return 1.0;
+  double h0 = 1.0, h1 = x;
+  for (int k = 1; k < n; ++k) {
+    double h2 = x * h1 - k * h0;
+    h0 = h1; h1 = h2;
+  }
+  return h1;
+}
+
+/* C_n: the largest root of He_n (Sec. 2.4, eq. (18)).  Newton's method from
+ * the right of all roots; He_n' = n He_{n-1}.  Monotone for real-rooted
+ * polynomials. */
+double orc_cmax(int n) {
+  if (n == 1) return 0.0;
+  double x = 2.0 * sqrt((double)n) + 1.0;
+  for (int it = 0; it < 200; ++it) {
+    double dx = hermite(n, x) / (n * hermite(n - 1, x));
+    x -= dx;
+    if (fabs(dx) < 1e-16 * fabs(x)) break;
+  }
+  return x;
+}
+
+/* ------------------------------------------------------------------ */
+/* Basis change F_M^[u,th] -> F_M^[u~,th~] (Sec. 2.3).                */
+/* The paper cites an O(M^3) algorithm without printing it.  Used here: */
+/* from dH_alpha/du_d = H_{alpha+e_d} and dH_alpha/dth = 1/2 sum_d       */
+/* H_{alpha+2e_d} (both follow from the definition of H in Sec. 2.2),   */
+/* H^[u,th]_alpha = sum_k prod_d c^(d)_k H^[u~,th~]_{alpha+k}, with     */
+/* c^(d) the Taylor coefficients of exp(-du_d t - dth t^2/2).  Applied  */
+/* one dimension at a time; exact for |alpha| <= M.                      */
+/* ------------------------------------------------------------------ */
+void orc_basis_change(int M, const double *f, const double *from, const double *to,
+                      double *out) {
+  const idxset *s = idx_of(M);
+  int N = s->N;
+  double du[3] = {to[0] - from[0], to[1] - from[1], 0.0};
+  double dth = to[2] - from[2];
+  double *tmp = (double *)malloc(sizeof(double) * N);
+  memcpy(tmp, f, sizeof(double) * N);
+  for (int d = 0; d < 3; ++d) {
+    double c[MMAX + 2];
+    c[0] = 1.0;
+    c[1] = -du[d];
+    for (int n = 1; n < M; ++n) c[n + 1] = (-du[d] * c[n] - dth * c[n - 1]) / (n + 1);
+    for (int al = 0; al < N; ++al) {
+      int ad = s->a[3 * al + d];
+      double acc = 0.0;
+      for (int k = 0; k <= ad; ++k) acc += c[k] * tmp[shifted(s, al, d, -k)];
+      out[al] = acc;
+    }
+    memcpy(tmp, out, sizeof(double) * N);
+  }
+  free(tmp);
+}
+
+/* Pi_M(xi_d f) in f's own basis: from xi_d = u_d + sqrt(th) v_d and
+ * v He_n(v) = He_{n+1}(v) + n He_{n-1}(v):
+ *   (xi_d f)_alpha = th f_{alpha-e_d} + u_d f_alpha + (alpha_d + 1) f_{alpha+e_d}. */
+void orc_xi_mult(int M, int d, const double *f, const double *basis, double *out) {
+  const idxset *s = idx_of(M);
+  double ud = (d < 2) ? basis[d] : 0.0, th = basis[2];
+  for (int al = 0; al < s->N; ++al) {
+    int lo = shifted(s, al, d, -1), hi = shifted(s, al, d, +1);
+    double v = ud * f[al];
+    if (lo >= 0) v += th * f[lo];
+    if (hi >= 0) v += (s->a[3 * al + d] + 1) * f[hi];
+    out[al] = v;
+  }
+}
+
+/* Two-step update of Sec. 2.4: given coefficients in the old basis [u, th],
+ * recover (u', th') from eq. (3) and project into F_M^[u',th'].
+ *   rho u'_d = rho u_d + f_{e_d};
+ *   rho|u'|^2 + 3 rho th' = rho|u|^2 + 2 u.f_e + 3 rho th + 2 sum_d f_{2e_d}.
+ * Afterwards eq. (10) holds: f_e = 0 and sum_d f_{2e_d} = 0, set exactly
+ * (f_{2e_3} is the dependent coefficient, Sec. 2.2).  Returns -1 if rho <= 0
+ * or th' <= 0 or a value is not finite. */
+int orc_normalise(int M, double *rec) {
+  const idxset *s = idx_of(M);
+  double *f = rec + 3;
+  double rho = f[0];
+  int e[3] = {P3(s, 1, 0, 0), P3(s, 0, 1, 0), P3(s, 0, 0, 1)};
+  int e2[3] = {P3(s, 2, 0, 0), P3(s, 0, 2, 0), P3(s, 0, 0, 2)};
+  if (!(rho > 0.0) || !isfinite(rho)) return -1;
+  double u[3] = {rec[0], rec[1], 0.0}, th = rec[2];
+  double fe2 = 0.0, tr = 0.0, un[3];
+  for (int d = 0; d < 3; ++d) {
+    un[d] = u[d] + f[e[d]] / rho;
+    fe2 += f[e[d]] * f[e[d]];
+    tr += f[e2[d]];
+  }
+  double thn = th + (2.0 * tr - fe2 / rho) / (3.0 * rho);
+  if (!(thn > 0.0) || !isfinite(thn) || !isfinite(un[0]) || !isfinite(un[1])) return -1;
+  double from[3] = {u[0], u[1], th}, to[3] = {un[0], un[1], thn};
+  double *g = (double *)malloc(sizeof(double) * s->N);
+  orc_basis_change(M, f, from, to, g);
+  memcpy(f, g, sizeof(double) * s->N);
+  free(g);
+  for (int d = 0; d < 3; ++d) f[e[d]] = 0.0;
+  f[e2[2]] = -(f[e2[0]] + f[e2[1]]);
+  rec[0] = un[0]; rec[1] = un[1]; rec[2] = thn;
+  for (int al = 0; al < s->N; ++al)
+    if (!isfinite(f[al])) return -1;
+  return 0;
+}
+
+/* Macroscopic quantities from eq. (10): rho = f_0, u from the basis,
+ * sigma_ij = (1 + delta_ij) f_{e_i+e_j}, q_i = 2 f_{3e_i} + sum_d f_{2e_d+e_i}. */
+void orc_macro(int M, const double *rec, double *out) {
+  const idxset *s = idx_of(M);
+  const double *f = rec + 3;
+  out[0] = f[0]; out[1] = rec[0]; out[2] = rec[1]; out[3] = rec[2];
+  out[4] = 2.0 * f[P3(s, 2, 0, 0)];
+  out[5] = f[P3(s, 1, 1, 0)];
+  out[6] = 2.0 * f[P3(s, 0, 2, 0)];
+  out[7] = 2.0 * f[P3(s, 0, 0, 2)];
+  for (int i = 0; i < 3; ++i) {
+    int b3[3] = {0, 0, 0};
+    b3[i] = 3;
+    double q = 2.0 * f[P3(s, b3[0], b3[1], b3[2])];
+    for (int d = 0; d < 3; ++d) {
+      int b[3] = {0, 0, 0};
+      b[d] += 2; b[i] += 1;
+      q += f[P3(s, b[0], b[1], b[2])];
+    }
+    out[8 + i] = q;
+  }
+}
+
+/* BGK-type relaxation Q = nu (f^E - f), eq. (5), with the collision
+ * frequency of eq. (29).  BGK: f^E is the local Maxwellian, eq. (6), whose
+ * only coefficient in the cell's own basis is f^E_0 = rho.  Shakhov, eq. (8):
+ * (1-Pr)(xi-u).q/(5 rho th^2)(|xi-u|^2/th - 5) expands in Hermite
+ * polynomials to (1-Pr)/(5 rho th^(3/2)) sum_i q_i (He_{3e_i} +
+ * sum_{d!=i} He_{e_i+2e_d}), giving f^E_{3e_i} = f^E_{e_i+2e_d} =
+ * (1-Pr) q_i / 5.  Requires M >= 3. */
+void orc_collision(const orc_problem *P, const double *rec, double *Q) {
+  int M = P->M;
+  const idxset *s = idx_of(M);
+  const double *f = rec + 3;
+  double rho = f[0], th = rec[2];
+  double nu = P->beta * sqrt(M_PI / 2.0) * rho * pow(th, 1.0 - P->omega) / P->Kn;
+  double *fE = (double *)calloc(s->N, sizeof(double));
+  fE[0] = rho;
+  if (P->collision == 1) {
+    double mac[11];
+    orc_macro(M, rec, mac);
+    for (int i = 0; i < 3; ++i) {
+      double c = (1.0 - P->Pr) * mac[8 + i] / 5.0;
+      int b3[3] = {0, 0, 0};
+      b3[i] = 3;
+      fE[P3(s, b3[0], b3[1], b3[2])] += c;
+      for (int d = 0; d < 3; ++d) {
+        if (d == i) continue;
+        int b[3] = {0, 0, 0};
+        b[i] = 1; b[d] = 2;
+        fE[P3(s, b[0], b[1], b[2])] += c;
+      }
+    }
+  }
+  for (int al = 0; al < s->N; ++al) Q[al] = nu * (fE[al] - f[al]);
+  free(fE);
+}
+
+/* Regularisation term (Sec. 2.2, eq. (12); reading: the globally hyperbolic
+ * system replaces Pi(xi_d d_d f) by Pi(xi_d Pi d_d f)).  The difference is
+ * the order-(M+1) part of d_d f carried down by xi_d:
+ *   G_b = (b_d + 1) [sum_k f_{b+e_d-e_k} du_k + 1/2 sum_k f_{b+e_d-2e_k} dth],
+ * for |b| = M, zero below; du_3 = 0. */
+void orc_regularisation(int M, int d, const double *f, double du1, double du2, double dth,
+                        double *G) {
+  const idxset *s = idx_of(M);
+  double du[3] = {du1, du2, 0.0};
+  for (int b = 0; b < s->N; ++b) {
+    G[b] = 0.0;
+    if (deg(s, b) != M) continue;
+    int bb[3] = {s->a[3 * b], s->a[3 * b + 1], s->a[3 * b + 2]};
+    bb[d] += 1; /* gamma = b + e_d, |gamma| = M + 1 */
+    double acc = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      int g1[3] = {bb[0], bb[1], bb[2]};
+      g1[k] -= 1;
+      int i1 = P3(s, g1[0], g1[1], g1[2]);
+      if (i1 >= 0) acc += f[i1] * du[k];
+      int g2[3] = {bb[0], bb[1], bb[2]};
+      g2[k] -= 2;
+      int i2 = P3(s, g2[0], g2[1], g2[2]);
+      if (i2 >= 0) acc += 0.5 * f[i2] * dth;
+    }
+    G[b] = (s->a[3 * b + d] + 1) * acc;
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* Diffuse (Maxwell, full accommodation) wall, Sec. 2.3 and Sec. 4.   */
+/* Reading: kinetic half-range flux.  Outward normal n = sig e_d.      */
+/* Leaving half: Pi[(xi.n) 1_{xi.n>0} f_cell] in the cell basis.      */
+/* Entering half: rho_w (xi.n) 1_{xi.n<0} Maxwellian(u_w, th_w), with  */
+/* rho_w fixed by zero net mass flux, projected into the cell basis.   */
+/* In 1-D, for w = sig v, a = sig u_d / sqrt(th):                       */
+/*  J+_kl(a) = (2pi)^-1/2 int_{-a}^inf He_k(w) He_l(w) (a+w) e^{-w^2/2} */
+/* ------------------------------------------------------------------ */
+
+/* K_n(a) = (2pi)^-1/2 int_{-a}^inf He_n(w) e^{-w^2/2} dw */
+static double halfK(int n, double a) {
+  if (n == 0) return 0.5 * erfc(-a / sqrt(2.0));
+  return hermite(n - 1, -a) * exp(-0.5 * a * a) / sqrt(2.0 * M_PI);
+}
+
+static double binom(int n, int k) {
+  return factorial(n) / (factorial(k) * factorial(n - k));
+}
+
+/* I_kl(a) = (2pi)^-1/2 int_{-a}^inf He_k He_l e^{-w^2/2}, using the
+ * linearisation He_k He_l = sum_j C(k,j) C(l,j) j! He_{k+l-2j}. */
+static double halfI(int k, int l, double a) {
+  if (l < 0) return 0.0;
+  double acc = 0.0;
+  int jm = k < l ? k : l;
+  for (int j = 0; j <= jm; ++j) acc += binom(k, j) * binom(l, j) * factorial(j) * halfK(k + l - 2 * j, a);
+  return acc;
+}
+
+static double halfJplus(int k, int l, double a) {
+  return a * halfI(k, l, a) + halfI(k, l + 1, a) + l * halfI(k, l - 1, a);
+}
+
+void orc_wall_flux(const orc_problem *P, int wall, const double *rec, double *phi) {
+  int M = P->M;
+  const idxset *s = idx_of(M);
+  const double *f = rec + 3;
+  int d = (wall == 0 || wall == 2) ? 1 : 0;
+  double sig = (wall == 1 || wall == 2) ? 1.0 : -1.0;
+  double th = rec[2], sq = sqrt(th);
+  double a = sig * rec[d] / sq;
+  /* leaving half, cell basis */
+  for (int al = 0; al < s->N; ++al) {
+    int ad = s->a[3 * al + d];
+    double acc = 0.0;
+    for (int bd = 0; bd <= M; ++bd) {
+      int b[3] = {s->a[3 * al], s->a[3 * al + 1], s->a[3 * al + 2]};
+      b[d] = bd;
+      int ib = P3(s, b[0], b[1], b[2]);
+      if (ib < 0) continue;
+      double sgn = ((ad + bd) % 2 == 0) ? 1.0 : sig;
+      acc += f[ib] * pow(th, 0.5 * (ad - bd)) * sq * sgn * halfJplus(ad, bd, a) / factorial(ad);
+    }
+    phi[al] = acc;
+  }
+  /* entering half, wall basis [u_w, th_w] (u_w tangential, so a = 0) */
+  double thw = P->wall_theta[wall], sqw = sqrt(thw);
+  double rhow = phi[0] * sqrt(2.0 * M_PI / thw);
+  double *psi = (double *)calloc(s->N, sizeof(double));
+  for (int k = 0; k <= M; ++k) {
+    int b[3] = {0, 0, 0};
+    b[d] = k;
+    double jfull = (k == 1) ? 1.0 : 0.0;
+    double jminus = jfull - halfJplus(k, 0, 0.0);
+    double sgn = (k % 2 == 0) ? 1.0 : sig;
+    psi[P3(s, b[0], b[1], b[2])] = rhow * pow(thw, 0.5 * k) * sqw * sgn * jminus / factorial(k);
+  }
+  double wb[3] = {0.0, 0.0, thw};
+  wb[1 - d] = P->wall_u[wall]; /* tangential direction */
+  double *t = (double *)malloc(sizeof(double) * s->N);
+  orc_basis_change(M, psi, wb, rec, t);
+  for (int al = 0; al < s->N; ++al) phi[al] += t[al];
+  free(t);
+  free(psi);
+}
+
+/* ------------------------------------------------------------------ */
+/* Interior face (Sec. 2.3, eq. (14)).  Reading: HLL flux with signal  */
+/* speeds u_d -/+ C_{M+1} sqrt(th) (the characteristic speeds used in  */
+/* the CFL condition eq. (18)); F(f) = Pi_M(xi_d f) in f's own basis;   */
+/* both halves projected into the requested basis.  The non-            */
+/* conservative regularisation jump g (straight path in (u, th, f))    */
+/* is split w- to the left cell and w+ to the right cell.               */
+/* ------------------------------------------------------------------ */
+void orc_face_flux(const orc_problem *P, int d, const double *recL, const double *recR,
+                   const double *basis, double *F, double *g, double *wm, double *wp) {
+  int M = P->M;
+  const idxset *s = idx_of(M);
+  int N = s->N;
+  double C = orc_cmax(M + 1);
+  double cL = C * sqrt(recL[2]), cR = C * sqrt(recR[2]);
+  double lamL = fmin(recL[d] - cL, recR[d] - cR);
+  double lamR = fmax(recL[d] + cL, recR[d] + cR);
+  double *FL = (double *)malloc(sizeof(double) * N), *FR = (double *)malloc(sizeof(double) * N);
+  double *AL = (double *)malloc(sizeof(double) * N), *AR = (double *)malloc(sizeof(double) * N);
+  double *t = (double *)malloc(sizeof(double) * N);
+  orc_xi_mult(M, d, recL + 3, recL, FL);
+  orc_xi_mult(M, d, recR + 3, recR, FR);
+  if (lamL >= 0.0) {
+    for (int al = 0; al < N; ++al) { AL[al] = FL[al]; AR[al] = 0.0; }
+    *wm = 0.0; *wp = 1.0;
+  } else if (lamR <= 0.0) {
+    for (int al = 0; al < N; ++al) { AL[al] = 0.0; AR[al] = FR[al]; }
+    *wm = 1.0; *wp = 0.0;
+  } else {
+    double den = lamR - lamL;
+    for (int al = 0; al < N; ++al) {
+      AL[al] = (lamR * FL[al] - lamL * lamR * recL[3 + al]) / den;
+      AR[al] = (-lamL * FR[al] + lamL * lamR * recR[3 + al]) / den;
+    }
+    *wm = -lamL / den; *wp = lamR / den;
+  }
+  orc_basis_change(M, AL, recL, basis, F);
+  orc_basis_change(M, AR, recR, basis, t);
+  for (int al = 0; al < N; ++al) F[al] += t[al];
+  double *avg = FL; /* reuse */
+  for (int al = 0; al < N; ++al) avg[al] = 0.5 * (recL[3 + al] + recR[3 + al]);
+  orc_regularisation(M, d, avg, recR[0] - recL[0], recR[1] - recL[1], recR[2] - recL[2], g);
+  free(FL); free(FR); free(AL); free(AR); free(t);
+}
+
+/* ------------------------------------------------------------------ */
+/* Level helpers                                                       */
+/* ------------------------------------------------------------------ */
+void orc_level_shape(const orc_problem *P, int level, int *nx, int *ny) {
+  *nx = P->nx >> level;
+  *ny = P->ny >> level;
+}
+
+static int rlen(const orc_problem *P) { return orc_nalpha(P->M) + 3; }
+
+static const double *cell(const orc_problem *P, int nx, const double *st, int i, int j) {
+  return st + (size_t)(j * nx + i) * rlen(P);
+}
+
+static double minmod(double a, double b) {
+  if (a > 0.0 && b > 0.0) return fmin(a, b);
+  if (a < 0.0 && b < 0.0) return fmax(a, b);
+  return 0.0;
+}
+
+/* Face state of cell (i, j) on its side `side` (+1: x_{i+1/2} / y_{j+1/2},
+ * -1: x_{i-1/2} / y_{j-1/2}) in direction d, eq. (15): every variable of the
+ * record (u1, u2, th, f_alpha) gets v +/- (dx/2) slope.  First order: zero
+ * slope.  Second order: central slope (paper) or minmod of the one-sided
+ * differences; zero slope for the first and last cell in direction d. */
+static void face_state(const orc_problem *P, int nx, int ny, const double *st, int i, int j,
+                       int d, int side, double *out) {
+  int R = rlen(P);
+  const double *c = cell(P, nx, st, i, j);
+  int n = d == 0 ? nx : ny, k = d == 0 ? i : j;
+  if (P->order == 1 || k == 0 || k == n - 1) {
+    memcpy(out, c, sizeof(double) * R);
+    return;
+  }
+  const double *lo = d == 0 ? cell(P, nx, st, i - 1, j) : cell(P, nx, st, i, j - 1);
+  const double *hi = d == 0 ? cell(P, nx, st, i + 1, j) : cell(P, nx, st, i, j + 1);
+  for (int v = 0; v < R; ++v) {
+    double sl = P->limiter == 1 ? 0.5 * (hi[v] - lo[v]) : minmod(hi[v] - c[v], c[v] - lo[v]);
+    out[v] = c[v] + 0.5 * side * sl;
+  }
+}
+
+/* R_ij(f) of eq. (13) in the basis of cell (i, j): face fluxes (eq. (14),
+ * reconstruction eq. (15)), regularisation jumps at faces and inside the
+ * cell, wall fluxes and the collision term. */
+int orc_cell_residual(const orc_problem *P, int level, const double *st, int i, int j, double *Rv) {
+  int nx, ny;
+  orc_level_shape(P, level, &nx, &ny);
+  int M = P->M, N = orc_nalpha(M), R = N + 3;
+  double dx = P->lx / nx, dy = P->ly / ny;
+  const double *c = cell(P, nx, st, i, j);
+  double *own = (double *)malloc(sizeof(double) * R), *nb = (double *)malloc(sizeof(double) * R);
+  double *F = (double *)malloc(sizeof(double) * N), *g = (double *)malloc(sizeof(double) * N);
+  double *q = (double *)malloc(sizeof(double) * N);
+  for (int al = 0; al < N; ++al) Rv[al] = 0.0;
+  for (int d = 0; d < 2; ++d) {
+    double h = d == 0 ? dx : dy;
+    int n = d == 0 ? nx : ny, k = d == 0 ? i : j;
+    double jump[3];
+    for (int side = +1; side >= -1; side -= 2) {
+      face_state(P, nx, ny, st, i, j, d, side, own);
+      if (side == +1) { jump[0] = own[0]; jump[1] = own[1]; jump[2] = own[2]; }
+      else { jump[0] -= own[0]; jump[1] -= own[1]; jump[2] -= own[2]; }
+      int kn = k + side;
+      if (kn < 0 || kn >= n) {
+        int wall = d == 0 ? (side > 0 ? 1 : 3) : (side > 0 ? 2 : 0);
+        orc_wall_flux(P, wall, own, F); /* outward flux */
+        for (int al = 0; al < N; ++al) Rv[al] -= F[al] / h;
+        continue;
+      }
+      int in = d == 0 ? kn : i, jn = d == 0 ? j : kn;
+      face_state(P, nx, ny, st, in, jn, d, -side, nb);
+      double wm, wp;
+      if (side == +1) {
+        orc_face_flux(P, d, own, nb, c, F, g, &wm, &wp);
+        for (int al = 0; al < N; ++al) Rv[al] += (-F[al] + wm * g[al]) / h;
+      } else {
+        orc_face_flux(P, d, nb, own, c, F, g, &wm, &wp);
+        for (int al = 0; al < N; ++al) Rv[al] += (F[al] + wp * g[al]) / h;
+      }
+    }
+    /* regularisation inside the cell: jump from the (-) face to the (+) face */
+    orc_regularisation(M, d, c + 3, jump[0], jump[1], jump[2], g);
+    for (int al = 0; al < N; ++al) Rv[al] += g[al] / h;
+  }
+  orc_collision(P, c, q);
+  for (int al = 0; al < N; ++al) Rv[al] += q[al];
+  free(own); free(nb); free(F); free(g); free(q);
+  return 0;
+}
+
+/* Local time step of eq. (18) at the CFL number, optionally capped so that
+ * nu*dt <= nu_dt_cap (explicit relaxation stays stable for stiff cells). */
+double orc_local_dt(const orc_problem *P, int level, const double *rec) {
+  int nx, ny;
+  orc_level_shape(P, level, &nx, &ny);
+  double dx = P->lx / nx, dy = P->ly / ny;
+  double C = orc_cmax(P->M + 1), sq = sqrt(rec[2]);
+  double dt = P->cfl / ((fabs(rec[0]) + C * sq) / dx + (fabs(rec[1]) + C * sq) / dy);
+  if (P->nu_dt_cap > 0.0) {
+    double nu = P->beta * sqrt(M_PI / 2.0) * rec[3] * pow(rec[2], 1.0 - P->omega) / P->Kn;
+    if (nu * dt > P->nu_dt_cap) dt = P->nu_dt_cap / nu;
+  }
+  return dt;
+}
+
+/* Weighted L2 norm of Sec. 3.2.3, eq. (28): per cell
+ * ||R_ij||^2 = sum_alpha alpha! th^-|alpha| R_alpha^2 (the inner product of
+ * F_M^[u,th] with weight 1/Maxwellian), area-weighted, divided by LxLy. */
+double orc_norm(const orc_problem *P, int level, const double *Rrec) {
+  int nx, ny;
+  orc_level_shape(P, level, &nx, &ny);
+  const idxset *s = idx_of(P->M);
+  int R = s->N + 3;
+  double ds = (P->lx / nx) * (P->ly / ny), acc = 0.0;
+  for (int c = 0; c < nx * ny; ++c) {
+    const double *r = Rrec + (size_t)c * R;
+    double th = r[2], loc = 0.0;
+    for (int al = 0; al < s->N; ++al) {
+      double w = factorial(s->a[3 * al]) * factorial(s->a[3 * al + 1]) * factorial(s->a[3 * al + 2]);
+      loc += w * pow(th, -deg(s, al)) * r[3 + al] * r[3 + al];
+    }
+    acc += loc * ds;
+  }
+  return sqrt(acc / (P->lx * P->ly));
+}
+
+/* Residual record (basis of the cell) of r - R(f) (Alg. 2), r projected into
+ * the cell's current basis.  rhs == NULL means r = 0. */
+static int cell_defect(const orc_problem *P, int level, const double *st, const double *rhs, int i,
+                       int j, double *out /* N+3 */) {
+  int nx, ny;
+  orc_level_shape(P, level, &nx, &ny);
+  int N = orc_nalpha(P->M);
+  const double *c = cell(P, nx, st, i, j);
+  double *Rv = (double *)malloc(sizeof(double) * N);
+  orc_cell_residual(P, level, st, i, j, Rv);
+  out[0] = c[0]; out[1] = c[1]; out[2] = c[2];
+  for (int al = 0; al < N; ++al) out[3 + al] = -Rv[al];
+  if (rhs) {
+    const double *r = cell(P, nx, rhs, i, j);
+    orc_basis_change(P->M, r + 3, r, c, Rv);
+    for (int al = 0; al < N; ++al) out[3 + al] += Rv[al];
+  }
+  free(Rv);
+  return 0;
+}
+
+int orc_residual(const orc_problem *P, int level, const double *st, const double *rhs, double *Rbar,
+                 double *norm) {
+  int nx, ny;
+  orc_level_shape(P, level, &nx, &ny);
+  int R = rlen(P);
+  (void)idx_of(P->M); /* build the index table before the parallel region */
+  double *buf = Rbar ? Rbar : (double *)malloc(sizeof(double) * R * nx * ny);
+#pragma omp parallel for schedule(static)
+  for (int c = 0; c < nx * ny; ++c) cell_defect(P, level, st, rhs, c % nx, c / nx, buf + (size_t)c * R);
+  if (norm) *norm = orc_norm(P, level, buf);
+  if (!Rbar) free(buf);
+  return 0;
+}
+
+double orc_mass(const orc_problem *P, int level, const double *st) {
+  int nx, ny;
+  orc_level_shape(P, level, &nx, &ny);
+  int R = rlen(P);
+  double ds = (P->lx / nx) * (P->ly / ny), m = 0.0;
+  for (int c = 0; c < nx * ny; ++c) m += st[(size_t)c * R + 3] * ds;
+  return m;
+}
+
+/* ------------------------------------------------------------------ */
+/* Fast sweeping, Sec. 3.1, eq. (20) and Alg. 1                        */
+/* ------------------------------------------------------------------ */
+
+/* One Gauss-Seidel cell update of Alg. 1: dt from the current state of the
+ * cell, f <- f + dt (R_ij(f) - r_ij) in the cell's basis, then the two-step
+ * normalisation of Sec. 2.4. */
+static int cell_update(const orc_problem *P, int level, double *st, const double *rhs, int i, int j) {
+  int nx, ny;
+  orc_level_shape(P, level, &nx, &ny);
+  int N = orc_nalpha(P->M), R = N + 3;
+  double *c = st + (size_t)(j * nx + i) * R;
+  double dt = orc_local_dt(P, level, c);
+  double *d = (double *)malloc(sizeof(double) * R);
+  cell_defect(P, level, st, rhs, i, j, d); /* r - R */
+  for (int al = 0; al < N; ++al) c[3 + al] -= dt * d[3 + al];
+  free(d);
+  return orc_normalise(P->M, c);
+}
+
+/* Sweep direction k (0..3 = D1..D4): i from the left (D1, D4) or right
+ * (D2, D3) as outer loop, j upward (D1, D2) or downward (D3, D4) inner. */
+static int sweep_dir(const orc_problem *P, int level, double *st, const double *rhs, int k,
+                     int wavefront) {
+  int nx, ny;
+  orc_level_shape(P, level, &nx, &ny);
+  int irev = (k == 1 || k == 2), jrev = (k == 2 || k == 3);
+  int bad = 0;
+  (void)idx_of(P->M); /* build the index table before the parallel region */
+  if (!wavefront) {
+    for (int a = 0; a < nx; ++a)
+      for (int b = 0; b < ny; ++b) {
+        int i = irev ? nx - 1 - a : a, j = jrev ? ny - 1 - b : b;
+        if (cell_update(P, level, st, rhs, i, j)) bad = 1;
+      }
+    return bad ? -1 : 0;
+  }
+  /* anti-diagonals a + b = t of the sweep coordinates: every cell of the
+   * cross-shaped radius-2 stencil lies on another diagonal, earlier ones
+   * already updated and later ones not, exactly as in the serial order. */
+  for (int t = 0; t <= nx + ny - 2; ++t) {
+    int a0 = t - (ny - 1) > 0 ? t - (ny - 1) : 0, a1 = t < nx - 1 ? t : nx - 1;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int a = a0; a <= a1; ++a) {
+      int b = t - a;
+      int i = irev ? nx - 1 - a : a, j = jrev ? ny - 1 - b : b;
+      if (cell_update(P, level, st, rhs, i, j)) bad |= 1;
+    }
+  }
+  return bad ? -1 : 0;
+}
+
+int orc_sweep(const orc_problem *P, int level, double *st, const double *rhs, int dir_mask, int nsteps,
+              int wavefront) {
+  for (int s = 0; s < nsteps; ++s)
+    for (int k = 0; k < 4; ++k)
+      if (dir_mask & (1 << k))
+        if (sweep_dir(P, level, st, rhs, k, wavefront)) return -1;
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Multigrid, Sec. 3.2                                                 */
+/* ------------------------------------------------------------------ */
+
+/* Restriction (Sec. 3.2.2): coarse cell (I, J) is made of fine cells
+ * (2I, 2J), (2I+1, 2J), (2I, 2J+1), (2I+1, 2J+1).  (u_H, th_H) from
+ * conservation of mass, momentum and energy, eq. (24); coefficients are the
+ * area average of the children projected into that basis, eq. (25); the
+ * residual records are restricted the same way into the same basis. */
+int orc_restrict(const orc_problem *P, int level_fine, const double *fine, const double *fineR,
+                 double *coarse, double *coarseR) {
+  int nx, ny;
+  orc_level_shape(P, level_fine, &nx, &ny);
+  int cnx = nx / 2, cny = ny / 2, M = P->M, N = orc_nalpha(M), R = N + 3;
+  const idxset *s = idx_of(M);
+  double dsh = (P->lx / nx) * (P->ly / ny), dsH = 4.0 * dsh;
+  int bad = 0;
+  double *t = (double *)malloc(sizeof(double) * N);
+  for (int J = 0; J < cny; ++J)
+    for (int I = 0; I < cnx; ++I) {
+      const double *ch[4] = {cell(P, nx, fine, 2 * I, 2 * J), cell(P, nx, fine, 2 * I + 1, 2 * J),
+                             cell(P, nx, fine, 2 * I, 2 * J + 1), cell(P, nx, fine, 2 * I + 1, 2 * J + 1)};
+      double mass = 0.0, mom[2] = {0.0, 0.0}, en = 0.0;
+      for (int c = 0; c < 4; ++c) {
+        double rho = ch[c][3], u1 = ch[c][0], u2 = ch[c][1], th = ch[c][2];
+        mass += rho * dsh;
+        mom[0] += rho * u1 * dsh;
+        mom[1] += rho * u2 * dsh;
+        en += (rho * (u1 * u1 + u2 * u2) + 3.0 * rho * th) * dsh;
+      }
+      double rhoH = mass / dsH, uH1 = mom[0] / (rhoH * dsH), uH2 = mom[1] / (rhoH * dsH);
+      double thH = (en / dsH - rhoH * (uH1 * uH1 + uH2 * uH2)) / (3.0 * rhoH);
+      if (!(rhoH > 0.0) || !(thH > 0.0)) bad = 1;
+      double *out = coarse + (size_t)(J * cnx + I) * R;
+      out[0] = uH1; out[1] = uH2; out[2] = thH;
+      for (int al = 0; al < N; ++al) out[3 + al] = 0.0;
+      for (int c = 0; c < 4; ++c) {
+        orc_basis_change(M, ch[c] + 3, ch[c], out, t);
+        for (int al = 0; al < N; ++al) out[3 + al] += t[al] * dsh / dsH;
+      }
+      out[3 + P3(s, 1, 0, 0)] = 0.0;
+      out[3 + P3(s, 0, 1, 0)] = 0.0;
+      out[3 + P3(s, 0, 0, 1)] = 0.0;
+      out[3 + P3(s, 0, 0, 2)] = -(out[3 + P3(s, 2, 0, 0)] + out[3 + P3(s, 0, 2, 0)]);
+      if (fineR && coarseR) {
+        double *oR = coarseR + (size_t)(J * cnx + I) * R;
+        oR[0] = uH1; oR[1] = uH2; oR[2] = thH;
+        for (int al = 0; al < N; ++al) oR[3 + al] = 0.0;
+        for (int c = 0; c < 4; ++c) {
+          const double *rc = cell(P, nx, fineR, (c & 1) ? 2 * I + 1 : 2 * I, (c & 2) ? 2 * J + 1 : 2 * J);
+          orc_basis_change(M, rc + 3, rc, oR, t);
+          for (int al = 0; al < N; ++al) oR[3 + al] += t[al] * dsh / dsH;
+        }
+      }
+    }
+  free(t);
+  return bad ? -1 : 0;
+}
+
+/* Right-hand side of the coarse problem, eq. (22):
+ * r_H = R_H(I f_h) + I (r_h - R_h(f_h)), stored in the basis of I f_h. */
+int orc_fas_rhs(const orc_problem *P, int level_coarse, const double *coarse, const double *coarseRbar,
+                double *rhs) {
+  int nx, ny;
+  orc_level_shape(P, level_coarse, &nx, &ny);
+  int N = orc_nalpha(P->M), R = N + 3;
+  double *Rv = (double *)malloc(sizeof(double) * N);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const double *c = cell(P, nx, coarse, i, j);
+      const double *rb = cell(P, nx, coarseRbar, i, j);
+      double *o = rhs + (size_t)(j * nx + i) * R;
+      orc_cell_residual(P, level_coarse, coarse, i, j, Rv);
+      o[0] = c[0]; o[1] = c[1]; o[2] = c[2];
+      for (int al = 0; al < N; ++al) o[3 + al] = Rv[al] + rb[3 + al];
+    }
+  free(Rv);
+  return 0;
+}
+
+/* Coarse-grid correction with injection as prolongation, eq. (26):
+ * f^_h = f_h - I f_h + f~_H.  The difference of the two coarse states is
+ * formed in the basis of I f_h, projected into each child's basis, added,
+ * and the child is normalised.  A child that would become non-physical keeps
+ * its value (counted in the return value). */
+int orc_correct(const orc_problem *P, int level_fine, double *fine, const double *coarse_new,
+                const double *coarse_old) {
+  int nx, ny;
+  orc_level_shape(P, level_fine, &nx, &ny);
+  int cnx = nx / 2, cny = ny / 2, M = P->M, N = orc_nalpha(M), R = N + 3;
+  double *delta = (double *)malloc(sizeof(double) * N), *t = (double *)malloc(sizeof(double) * N);
+  double *keep = (double *)malloc(sizeof(double) * R);
+  int kept = 0;
+  for (int J = 0; J < cny; ++J)
+    for (int I = 0; I < cnx; ++I) {
+      const double *fn = cell(P, cnx, coarse_new, I, J), *fo = cell(P, cnx, coarse_old, I, J);
+      orc_basis_change(M, fn + 3, fn, fo, delta);
+      for (int al = 0; al < N; ++al) delta[al] -= fo[3 + al];
+      for (int c = 0; c < 4; ++c) {
+        int i = 2 * I + (c & 1), j = 2 * J + ((c & 2) ? 1 : 0);
+        double *ch = fine + (size_t)(j * nx + i) * R;
+        memcpy(keep, ch, sizeof(double) * R);
+        orc_basis_change(M, delta, fo, ch, t);
+        for (int al = 0; al < N; ++al) ch[3 + al] += t[al];
+        if (orc_normalise(M, ch)) {
+          memcpy(ch, keep, sizeof(double) * R);
+          ++kept;
+        }
+      }
+    }
+  free(delta); free(t); free(keep);
+  return kept;
+}
+
+/* One step of the (levels-level) NMG iteration, Alg. 2, on `level`
+ * (0 = finest here; the paper counts from the coarsest).  The coarsest
+ * solver is exactly s3 fast-sweeping steps. */
+int orc_vcycle(const orc_problem *P, int level, double *st, const double *rhs) {
+  if (level == P->levels - 1) return orc_sweep(P, level, st, rhs, 15, P->s3, 0);
+  int nx, ny;
+  orc_level_shape(P, level, &nx, &ny);
+  int R = rlen(P);
+  size_t nf = (size_t)nx * ny * R, nc = nf / 4;
+  if (orc_sweep(P, level, st, rhs, 15, P->s1, 0)) return -1;
+  double *Rb = (double *)malloc(sizeof(double) * nf);
+  double *fH = (double *)malloc(sizeof(double) * nc), *RH = (double *)malloc(sizeof(double) * nc);
+  double *rH = (double *)malloc(sizeof(double) * nc), *fT = (double *)malloc(sizeof(double) * nc);
+  int rc = 0;
+  orc_residual(P, level, st, rhs, Rb, NULL);
+  if (orc_restrict(P, level, st, Rb, fH, RH)) rc = -1;
+  if (!rc) {
+    orc_fas_rhs(P, level + 1, fH, RH, rH);
+    memcpy(fT, fH, sizeof(double) * nc);
+    for (int g = 0; g < P->gamma && !rc; ++g) rc = orc_vcycle(P, level + 1, fT, rH);
+  }
+  if (!rc) {
+    orc_correct(P, level, st, fT, fH);
+    rc = orc_sweep(P, level, st, rhs, 15, P->s2, 0);
+  }
+  free(Rb); free(fH); free(RH); free(rH); free(fT);
+  return rc;
+}
+
+/* Mass correction after each NMG iteration (Sec. 4): the boundary conditions
+ * leave the steady state determined only up to its total mass; every
+ * coefficient is scaled so that the total mass equals mass0 (u, th kept). */
+int orc_mass_fix(const orc_problem *P, double *st) {
+  if (!(P->mass0 > 0.0)) return 0;
+  double m = orc_mass(P, 0, st);
+  if (!(m > 0.0)) return -1;
+  double kappa = P->mass0 / m;
+  int R = rlen(P), N = R - 3;
+  for (int c = 0; c < P->nx * P->ny; ++c)
+    for (int al = 0; al < N; ++al) st[(size_t)c * R + 3 + al] *= kappa;
+  return 0;
+}
+
+/* NMG solver, Sec. 3.2.3: repeat NMG_K(f, 0) (+ mass correction) until the
+ * relative residual of eq. (28) is <= tol.  Returns 0 on convergence, 1 when
+ * max_cycles was reached, -1 on a non-physical state. */
+int orc_solve(const orc_problem *P, double *st, double tol, int max_cycles, double ref_norm,
+              int *cycles, double *hist) {
+  double nrm;
+  orc_residual(P, 0, st, NULL, NULL, &nrm);
+  if (!(ref_norm > 0.0)) ref_norm = nrm;
+  if (hist) hist[0] = nrm;
+  int n = 0;
+  while (n < max_cycles && !(nrm <= tol * ref_norm)) {
+    if (orc_vcycle(P, 0, st, NULL)) { *cycles = n; return -1; }
+    if (orc_mass_fix(P, st)) { *cycles = n; return -1; }
+    orc_residual(P, 0, st, NULL, NULL, &nrm);
+    ++n;
+    if (hist) hist[n] = nrm;
+    if (!isfinite(nrm)) { *cycles = n; return -1; }
+  }
+  *cycles = n;
+  return nrm <= tol * ref_norm ? 0 : 1;
+}
+
+/* Forward Euler / Richardson step of eq. (16) with the global step of
+ * eq. (17): all cells from the same old state, then normalised. */
+int orc_euler_step(const orc_problem *P, int level, double *st, double *dt_used) {
+  int nx, ny;
+  orc_level_shape(P, level, &nx, &ny);
+  int N = orc_nalpha(P->M), R = N + 3;
+  double dt = INFINITY;
+  for (int c = 0; c < nx * ny; ++c) {
+    double d = orc_local_dt(P, level, st + (size_t)c * R);
+    if (d < dt) dt = d;
+  }
+  double *Rb = (double *)malloc(sizeof(double) * R * nx * ny);
+  orc_residual(P, level, st, NULL, Rb, NULL); /* -R */
+  int bad = 0;
+  for (int c = 0; c < nx * ny; ++c) {
+    double *x = st + (size_t)c * R;
+    for (int al = 0; al < N; ++al) x[3 + al] -= dt * Rb[(size_t)c * R + 3 + al];
+    if (orc_normalise(P->M, x)) bad = 1;
+  }
+  free(Rb);
+  if (dt_used) *dt_used = dt;
+  return bad ? -1 : 0;
+}
+
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}

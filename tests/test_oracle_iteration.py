@@ -1,0 +1,180 @@
+"""Iteration-level pins of the oracle: fast sweeping (Alg. 1), the FAS
+V-cycle (Alg. 2), mass correction and the solver loop (Sec. 3.2.3)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2206_13164_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.mark.parametrize("order,limiter", [(1, 0), (2, 0), (2, 1)])
+def test_wavefront_order_equals_serial_order(orc, order, limiter):
+    # the anti-diagonal schedule reproduces the serial Gauss-Seidel order of
+    # each of D1..D4 bit for bit (cross-shaped radius-2 stencil)
+    s = I.spec(None, M=5, collision=1, Pr=2 / 3, nx=9, ny=7, order=order, limiter=limiter,
+               wall_u=[0.0, 0.0, 0.4, 0.0], wall_theta=[1.4, 1.0, 1.0, 1.0])
+    P = orc.problem(s)
+    st = I.random_state(s, seed=3)
+    rhs = I.random_rhs(s, 0, seed=4)
+    for mask in (1, 2, 4, 8, 15):
+        a, b = st.copy(), st.copy()
+        orc.sweep(P, 0, a, rhs=rhs, dir_mask=mask, nsteps=1, wavefront=False)
+        orc.set_threads(4)
+        orc.sweep(P, 0, b, rhs=rhs, dir_mask=mask, nsteps=1, wavefront=True)
+        orc.set_threads(1)
+        assert np.array_equal(a, b), mask
+
+
+def test_sweep_moves_towards_steady_state(orc):
+    s = I.spec("lid32_bgk_m3", nx=16, ny=16)
+    P = orc.problem(s)
+    st = I.maxwellian_state(s)
+    _, r0 = orc.residual(P, 0, st)
+    for _ in range(20):
+        orc.sweep(P, 0, st)
+        orc.mass_fix(P, st)
+    _, r1 = orc.residual(P, 0, st)
+    assert r1 < 0.2 * r0
+
+
+def test_fast_sweeping_and_euler_reach_the_same_state(orc):
+    # 8x8, config-1 physics, first order: explicit time marching (eq. (16),
+    # global step eq. (17), conserves mass) and fast sweeping with the mass
+    # correction converge to the same steady state
+    s = I.spec("lid32_bgk_m3", nx=8, ny=8, levels=1, s3=1)
+    P = orc.problem(s)
+    st_fs = I.maxwellian_state(s)
+    rc, cyc, hist = orc.solve(P, st_fs, 1e-12, 4000)
+    assert rc == 0
+    st_e = I.maxwellian_state(s)
+    m0 = orc.mass(P, 0, st_e)
+    _, r0 = orc.residual(P, 0, st_e)
+    for n in range(40000):
+        orc.euler_step(P, st_e)
+        if n % 10 == 0:
+            assert abs(orc.mass(P, 0, st_e) - m0) < 1e-13 * (n + 1)
+            _, r = orc.residual(P, 0, st_e)
+            if r <= 1e-12 * r0:
+                break
+    assert r <= 1e-12 * r0
+    assert np.max(np.abs(st_fs - st_e)) < 1e-9
+    assert cyc < n / 3  # fast sweeping needs far fewer iterations (Sec. 3.1)
+
+
+def test_nmg_and_single_level_fs_reach_the_same_state(orc):
+    s = I.spec("lid32_bgk_m3", nx=16, ny=16, levels=2)
+    P = orc.problem(s)
+    a = I.maxwellian_state(s)
+    rc, ca, _ = orc.solve(P, a, 1e-11, 200)
+    assert rc == 0
+    s1 = dict(s, levels=1, s3=1)
+    P1 = orc.problem(s1)
+    b = I.maxwellian_state(s1)
+    rc, cb, _ = orc.solve(P1, b, 1e-11, 5000)
+    assert rc == 0
+    assert np.max(np.abs(a - b)) < 1e-8
+    assert ca < cb / 4
+
+
+def test_restriction_conserves_mass_momentum_energy(orc):
+    s = I.spec(None, M=5, collision=1, Pr=2 / 3, nx=8, ny=8, order=2)
+    P = orc.problem(s)
+    st = I.random_state(s, seed=12, amp=0.08)
+    Rb, _ = orc.residual(P, 0, st)
+    c, cR = orc.restrict(P, 0, st, Rb)
+    for I_ in range(4):
+        for J in range(4):
+            ch = [st[2 * J + b // 2, 2 * I_ + b % 2] for b in range(4)]
+            rho = np.mean([x[3] for x in ch])
+            mom = np.mean([[x[3] * x[0], x[3] * x[1]] for x in ch], axis=0)
+            en = np.mean([x[3] * (x[0] ** 2 + x[1] ** 2 + 3 * x[2]) for x in ch])
+            C = c[J, I_]
+            assert abs(C[3] - rho) < 1e-14
+            assert np.allclose(C[3] * C[:2], mom, atol=1e-14)
+            assert abs(C[3] * (C[0] ** 2 + C[1] ** 2 + 3 * C[2]) - en) < 1e-13
+            assert C[4] == 0 and C[5] == 0 and C[6] == 0
+            assert abs(C[3 + 4] + C[3 + 7] + C[3 + 9]) < 1e-16
+            # the residual mass is the mean of the children's
+            assert abs(cR[J, I_][3] - np.mean([Rb[2 * J + b // 2, 2 * I_ + b % 2][3] for b in range(4)])) < 1e-13
+
+
+def test_correction_with_unchanged_coarse_state_is_identity(orc):
+    # f^ = f - I f + f~ with f~ = I f leaves f unchanged (eq. (26))
+    s = I.spec(None, M=5, nx=8, ny=8)
+    P = orc.problem(s)
+    st = I.random_state(s, seed=2)
+    c, _ = orc.restrict(P, 0, st)
+    out = st.copy()
+    kept = orc.correct(P, 0, out, c, c)
+    assert kept == 0
+    assert np.max(np.abs(out - st)) < 1e-14
+
+
+def test_fas_coarse_problem_is_solved_by_the_restriction(orc):
+    # with R_h(f_h) = r_h exactly (r_h := R_h(f_h)), the FAS right-hand side
+    # makes I f_h an exact coarse solution: r_H - R_H(I f_h) = 0
+    s = I.spec(None, M=5, collision=1, Pr=2 / 3, nx=8, ny=8, order=2)
+    P = orc.problem(s)
+    st = I.random_state(s, seed=6)
+    Rb, _ = orc.residual(P, 0, st, rhs=None)  # -R(f)
+    rhs = Rb.copy()
+    rhs[..., 3:] *= -1.0                      # r = R(f) in the cell basis
+    Rb2, n2 = orc.residual(P, 0, st, rhs=rhs)
+    assert n2 < 1e-13
+    c, cR = orc.restrict(P, 0, st, Rb2)
+    rH = orc.fas_rhs(P, 1, c, cR)
+    _, nH = orc.residual(P, 1, c, rhs=rH)
+    assert nH < 1e-13
+
+
+def test_mass_fix_restores_total_mass(orc):
+    s = I.spec("lid32_bgk_m3", nx=8, ny=8)
+    P = orc.problem(s)
+    st = I.random_state(s, seed=2)
+    orc.mass_fix(P, st)
+    assert abs(orc.mass(P, 0, st) - 1.0) < 1e-14
+
+
+def test_checkpoint_resume_is_bitwise(orc):
+    s = I.spec("lid32_bgk_m3", nx=16, ny=16)
+    P = orc.problem(s)
+    a = I.maxwellian_state(s)
+    _, r0 = orc.residual(P, 0, a)
+    rc, c1, _ = orc.solve(P, a, 0.0, 6, ref_norm=r0)
+    b = I.maxwellian_state(s)
+    orc.solve(P, b, 0.0, 2, ref_norm=r0)
+    ck = b.copy()
+    orc.solve(P, ck, 0.0, 4, ref_norm=r0)
+    assert np.array_equal(a, ck)
+
+
+def test_nonphysical_state_is_reported(orc):
+    s = I.spec("lid32_bgk_m3", nx=8, ny=8)
+    P = orc.problem(s)
+    st = I.maxwellian_state(s)
+    st[3, 4, 2] = -1.0  # negative temperature
+    with pytest.raises(FloatingPointError):
+        orc.sweep(P, 0, st)
+
+
+def test_paper_table1_iteration_counts(orc):
+    # Loose behavioural pin: Table 1 (Shakhov, Kn 0.1, M = 5, first order,
+    # lid 50 m/s, coarsest grid 8x8) prints about a dozen NMG iterations,
+    # nearly independent of the grid, and many more fast-sweeping iterations.
+    with open(os.path.join(GOLDEN, "paper_table1.json")) as fh:
+        g = json.load(fh)
+    orc.set_threads(8)
+    try:
+        s = I.spec("paper_table1_32")
+        P = orc.problem(s)
+        st = I.maxwellian_state(s)
+        rc, cyc, _ = orc.solve(P, st, 1e-8, 60)
+    finally:
+        orc.set_threads(1)
+    assert rc == 0
+    want = g["rows"]["32x32"]["NMG_iterations"]
+    assert abs(cyc - want) <= 3, (cyc, want)
