@@ -1,0 +1,181 @@
+"""Benchmark: steady-state NRxx solve of the lid-driven cavity on one MI355X.
+
+A step is one full solve (Alg. 2 V-cycles + mass correction + stop test,
+Sec. 3.2.3) from the global Maxwellian to the workload's tolerance, on the
+128x128 lid-driven cavity (Shakhov Pr 2/3, Kn 0.075, M = 5, second-order
+minmod, lid 0.5, 4-level V-cycle, tol 1e-10).  `value` is the whole-job
+smoother throughput: cell-moment updates made by fast-sweeping steps inside
+the timed region divided by the timed wall time.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "smoother cell-moment updates/s + time-to-residual 1e-8, plain vs mixed/learned"
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def per_update_cost(M: int, order: int, coarse: bool, fp_bytes: int = 8):
+    """Algorithmic cost of one cell update of the smoother (estimate of the
+    method, independent of the kernel): bytes = read + write of the cell
+    record (+ the right-hand-side record on coarse levels); flops = 3 C(M+4,4)
+    FMA per basis change times the number of changes (4 faces + normalise at
+    first order, 8 face states + normalise at second order, + 1 for the
+    right-hand side on coarse levels) plus ~80 flops per coefficient."""
+    N = math.comb(M + 3, 3)
+    P = (5 if order == 1 else 9) + (1 if coarse else 0)
+    flops = 2 * P * 3 * math.comb(M + 4, 4) + 80 * N
+    nbytes = 2 * (N + 3) * fp_bytes + ((N + 3) * fp_bytes if coarse else 0)
+    return flops, nbytes
+
+
+def cycle_accounting(spec):
+    """Cell updates, launches, flops and bytes of the smoother in one V-cycle."""
+    L = spec["levels"]
+    tot = dict(cells=0, launches=0, flops=0.0, bytes=0.0)
+    for k in range(L):
+        nx, ny = spec["nx"] >> k, spec["ny"] >> k
+        steps = spec["s3"] if k == L - 1 else spec["s1"] + spec["s2"]
+        fl, by = per_update_cost(spec["M"], spec["order"], coarse=k > 0)
+        cells = steps * 4 * nx * ny
+        tot["cells"] += cells
+        tot["launches"] += steps * 4 * (nx + ny - 1)
+        tot["flops"] += cells * fl
+        tot["bytes"] += cells * by
+    return tot
+
+
+def cpu_baseline(spec, seconds_hint: float):
+    """The oracle (FP64, serial paper-order sweeps, one thread) on a bounded
+    sample: one V-cycle of the same workload from the Maxwellian start."""
+    import oracle
+    from paper_2206_13164_amd import inputs as I
+    oracle.set_threads(1)
+    P = oracle.problem(spec)
+    st = I.maxwellian_state(spec)
+    acc = cycle_accounting(spec)
+    t0 = time.perf_counter()
+    oracle.vcycle(P, st)
+    dt = time.perf_counter() - t0
+    N = math.comb(spec["M"] + 3, 3)
+    return {"value": acc["cells"] * N / dt, "unit": "cell-moment updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"one V-cycle ({acc['cells']} cell updates) of the same workload from the "
+                      f"Maxwellian start, serial Gauss-Seidel order, 1 thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="lid128_shakhov_m5")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--max-cycles", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver's "
+              "multi-GPU decomposition is a design in DESIGN.md, not part of this build.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2206_13164_amd import inputs as I
+    from paper_2206_13164_amd import nrxx as N
+
+    spec = I.spec(args.workload)
+    tol = spec["tol"]
+    M = spec["M"]
+    NA = math.comb(M + 3, 3)
+    torch.cuda.set_device(0)
+    ctx = N.Context(spec)
+    st = ctx.empty(0)
+    ref = None
+
+    def one_solve():
+        ctx.init_maxwellian(st)
+        rc, cyc, hist = ctx.solve(st, tol, args.max_cycles, ref_norm=ref or 0.0)
+        return rc, cyc, hist
+
+    for _ in range(args.warmup):
+        rc, cyc, hist = one_solve()
+        ref = hist[0]
+    ctx.sweep_stats(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cycles = []
+    for _ in range(args.steps):
+        rc, cyc, hist = one_solve()
+        cycles.append(cyc)
+        if rc != N.NRXX_OK:
+            raise SystemExit(f"solve did not converge: rc={rc} cycles={cyc} last={hist[-1]:.3e}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sweep_ms, sweep_cells = ctx.sweep_stats(reset=True)
+    wall = t1 - t0
+    acc = cycle_accounting(spec)
+    ncyc = sum(cycles)
+    assert abs(sweep_cells - ncyc * acc["cells"]) < 0.5, (sweep_cells, ncyc * acc["cells"])
+    value = sweep_cells * NA / wall
+    launches = ncyc * acc["launches"]
+    avg_launch_s = sweep_ms * 1e-3 / launches
+    flops_per_launch = ncyc * acc["flops"] / launches
+    bytes_per_launch = ncyc * acc["bytes"] / launches
+    achieved_tflops = flops_per_launch / avg_launch_s / 1e12
+    achieved_gbs = bytes_per_launch / avg_launch_s / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-moment updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "grid": f"{spec['nx']}x{spec['ny']}", "M": M, "N_alpha": NA,
+            "collision": "Shakhov" if spec["collision"] else "BGK", "Kn": spec["Kn"],
+            "order": spec["order"], "limiter": "minmod" if spec["limiter"] == 0 else "central",
+            "levels": spec["levels"], "tol": tol, "start": "global Maxwellian",
+        },
+        "time_to_residual_s": wall / args.steps,
+        "cycles_per_solve": cycles,
+        "sweep_kernel_rate": sweep_cells * NA / (sweep_ms * 1e-3),
+        "sweep_share_of_wall": sweep_ms * 1e-3 / wall,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved_tflops,
+            "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved_tflops / PEAK_FP64_TFLOPS,
+            "traffic": None,
+            "kernel": "k_sweep_diag (one anti-diagonal of one sweep direction per launch)",
+            "avg_launch_us": avg_launch_s * 1e6,
+            "flops_per_launch": flops_per_launch,
+            "bytes_per_launch": bytes_per_launch,
+            "hbm_achieved_GBs": achieved_gbs,
+            "hbm_frac": achieved_gbs / PEAK_HBM_GBS,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, 20.0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

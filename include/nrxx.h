@@ -1,0 +1,182 @@
+/*
+ * nrxx.h -- C ABI of the MI355X (gfx950) steady-state solver for the
+ * Boltzmann equation with BGK-type collisions in the numerical regularized
+ * moment (NRxx) discretisation, with fast sweeping and the FAS nonlinear
+ * multigrid V-cycle of Hu & Li, "An efficient nonlinear multigrid solver for
+ * the simulation of rarefied gas cavity flow" (arXiv 2206.13164).
+ *
+ * Problem solved (Sec. 3, eq. (19) and (21)): on a rectangle of nx x ny
+ * uniform cells, find cell distributions f_ij in F_M^[u_ij, theta_ij]
+ * (Sec. 2.2, eq. (11)) with R_ij(f) = r_ij, where R_ij is the finite-volume
+ * operator of eq. (13) and r = 0 on the finest level.
+ *
+ * ---------------------------------------------------------------------------
+ * Memory layout of every per-cell object ("record"): device memory, FP64,
+ * cells in row-major order (cell (i, j) = column i, row j, i fastest, row
+ * j = 0 at y = 0), `nrxx_record_stride(M)` doubles per cell:
+ *     [u1, u2, theta, f_0, ..., f_{N-1}, padding]
+ * with N = (M+1)(M+2)(M+3)/6 coefficients in the graded order: |alpha| = 0..M;
+ * within one degree alpha_1 descending, then alpha_2 descending, alpha_3 =
+ * rest (so f_1, f_2, f_3 are f_{e_1}, f_{e_2}, f_{e_3}).  (u1, u2, theta) are
+ * the parameters of the Hermite basis the coefficients are expressed in.
+ * A state record satisfies eq. (10): f_0 = rho > 0, f_{e_i} = 0,
+ * f_{2e_1} + f_{2e_2} + f_{2e_3} = 0, theta > 0.  Coefficients with odd
+ * alpha_3 vanish for this two-dimensional, xi_3-even problem; the library
+ * treats them as zero on input and writes zeros.  Residual and right-hand
+ * side records use the same layout; their (u1, u2, theta) name the basis
+ * of their coefficients.  Padding entries are never read and are left as is.
+ *
+ * Walls are indexed S = 0 (y = 0), E = 1 (x = lx), N = 2 (y = ly),
+ * W = 3 (x = 0); all are fully diffuse (Sec. 4).
+ *
+ * Ownership: the caller owns every pointer passed in (state, residual and
+ * right-hand-side buffers, e.g. torch tensors' data pointers).  The context
+ * owns the coarse levels and scratch it allocates in nrxx_create and frees in
+ * nrxx_destroy.
+ *
+ * Ordering: all device work is enqueued on the stream given to nrxx_create.
+ * Calls that return host values (norm_out, mass_out, cycles_out, ...)
+ * synchronise that stream; the others return after enqueueing.
+ *
+ * Errors: every call returns an nrxx_status; nothing throws.  A call given
+ * invalid arguments changes nothing.  Non-physical states found by a kernel
+ * (rho <= 0, theta <= 0 or non-finite values) are reported by the next call
+ * that synchronises; the offending cell keeps its previous value.  The text
+ * of the last error is available from nrxx_last_error.  A context is not
+ * thread-safe; use one context per host thread and stream.
+ * ---------------------------------------------------------------------------
+ */
+#ifndef NRXX_H
+#define NRXX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nrxx_ctx nrxx_ctx;
+
+typedef enum {
+  NRXX_OK = 0,
+  NRXX_EINVAL = -1,    /* bad argument: see nrxx_last_error */
+  NRXX_ENONPHYS = -2,  /* rho <= 0 or theta <= 0 produced by an update */
+  NRXX_EDIVERGED = -3, /* non-finite residual norm */
+  NRXX_ENOMEM = -4,    /* device allocation failed */
+  NRXX_EHIP = -5,      /* HIP runtime error */
+  NRXX_EMAXIT = -6     /* nrxx_solve reached max_cycles (state is valid) */
+} nrxx_status;
+
+/* Problem description; dimensionless units (molecular mass 1, velocities in
+ * sqrt(theta_0)).  Sec. 4 fixes cfl = 0.9, s1 = s2 = 2, s3 = 4, omega = 0.81,
+ * beta = 1 (Shakhov and BGK), Pr = 2/3 (argon). */
+typedef struct {
+  int32_t nx, ny;         /* finest grid; both divisible by 2^(levels-1) */
+  double lx, ly;          /* domain size */
+  int32_t M;              /* expansion order, 3 <= M <= 8 */
+  int32_t collision;      /* 0 = BGK (eq. (6)), 1 = Shakhov (eq. (8)) */
+  double Pr, Kn, omega, beta; /* nu = beta sqrt(pi/2) rho theta^(1-omega) / Kn, eq. (29) */
+  int32_t order;          /* 1 or 2: spatial reconstruction, eq. (15) */
+  int32_t limiter;        /* order 2 only: 0 = minmod, 1 = central slopes */
+  double cfl;             /* CFL number of eq. (18) */
+  double nu_dt_cap;       /* > 0: the local step also obeys nu*dt <= nu_dt_cap */
+  double wall_u[4];       /* tangential wall speed (x for S/N, y for E/W) */
+  double wall_theta[4];   /* wall temperature */
+  int32_t levels;         /* multigrid levels K+1; level 0 = finest, levels-1 = coarsest */
+  int32_t s1, s2, s3;     /* pre-, post-smoothing and coarsest FS steps (Alg. 2) */
+  int32_t gamma;          /* 1 = V-cycle, 2 = W-cycle */
+  double mass0;           /* > 0: total mass restored after every cycle (Sec. 4); <= 0: off */
+  int32_t precision;      /* 0 = FP64 throughout (the only value accepted) */
+  int32_t schedule;       /* sweep schedule: 0 = automatic, 1 = one launch per diagonal */
+} nrxx_problem;
+
+/* Doubles per cell record for order M (N + 3 rounded up to a multiple of 8). */
+int32_t nrxx_record_stride(int32_t M);
+
+/* Create a context for `p` whose work is enqueued on `hip_stream` (a
+ * hipStream_t, NULL = the null stream).  Validates `p` (NRXX_EINVAL), builds
+ * the level hierarchy of Sec. 3.2.2 (coarse cell (I,J) = fine cells 2I..2I+1
+ * x 2J..2J+1) and allocates coarse levels and scratch (NRXX_ENOMEM).  On
+ * success *out is a new context; on failure *out is NULL. */
+int nrxx_create(const nrxx_problem *p, void *hip_stream, nrxx_ctx **out);
+
+/* Synchronise and free everything the context owns.  NULL is accepted. */
+int nrxx_destroy(nrxx_ctx *ctx);
+
+/* Text of the last error of this context ("" if none); valid until the next
+ * call on the context.  NULL gives the text of the last failed nrxx_create. */
+const char *nrxx_last_error(const nrxx_ctx *ctx);
+
+/* Cells of `level` (0 = finest). */
+int nrxx_level_shape(const nrxx_ctx *ctx, int level, int32_t *nx, int32_t *ny);
+
+/* Fill `state` (a level-`level` record array) with the global Maxwellian of
+ * density rho, velocity (u1, u2) and temperature theta (Sec. 4.1). */
+int nrxx_init_maxwellian(nrxx_ctx *ctx, int level, double *state, double rho, double u1,
+                         double u2, double theta);
+
+/* Defect of eq. (21)/(22) on `level`: R_out = r - R(f) per cell, expressed in
+ * the cell's current basis (Alg. 2, line "compute the fine grid residual"),
+ * with r projected from its own basis into the cell's.  rhs == NULL means
+ * r = 0.  R_out may be NULL.  If norm_out != NULL, writes the weighted L2
+ * norm of eq. (28) (per-cell weight alpha! theta^-|alpha|, area weighted,
+ * divided by lx*ly) and synchronises. */
+int nrxx_residual(nrxx_ctx *ctx, int level, const double *state, const double *rhs,
+                  double *R_out, double *norm_out);
+
+/* `nsteps` steps of the fast sweeping iteration, Alg. 1, in place on `state`
+ * (level `level`), for the right-hand side `rhs` (NULL: r = 0).  dir_mask bit
+ * k enables sweep direction D(k+1) of Sec. 3.1 (15 = the full step
+ * D1, D2, D3, D4).  Each cell update uses the local step of eq. (18) from the
+ * cell's current state, f <- f + dt (R_ij(f) - r_ij), then re-expands the
+ * cell in its new (u, theta) (Sec. 2.4).  The result equals the serial
+ * cell-by-cell order of the paper exactly: cells are updated along the
+ * anti-diagonals of each direction's order. */
+int nrxx_sweep(nrxx_ctx *ctx, int level, double *state, const double *rhs, int dir_mask, int nsteps);
+
+/* Restriction of Sec. 3.2.2: from level `level_fine` to level_fine + 1.
+ * (u_H, theta_H) by conservation of mass, momentum and energy (eq. (24)),
+ * coefficients averaged after projection into that basis (eq. (25)).  If
+ * fineR and coarseR are both non-NULL the residual records are restricted
+ * into the same basis. */
+int nrxx_restrict(nrxx_ctx *ctx, int level_fine, const double *fine, const double *fineR,
+                  double *coarse, double *coarseR);
+
+/* Coarse right-hand side of eq. (22): rhs = R_H(coarse) + coarseR, stored in
+ * the basis of `coarse` (level `level_coarse`). */
+int nrxx_fas_rhs(nrxx_ctx *ctx, int level_coarse, const double *coarse, const double *coarseR,
+                 double *rhs);
+
+/* Coarse-grid correction with injection as prolongation, eq. (26): each fine
+ * cell of level `level_fine` gets f + T(coarse_new - coarse_old) projected
+ * into its basis and re-expanded.  A cell that would become non-physical
+ * keeps its value. */
+int nrxx_correct(nrxx_ctx *ctx, int level_fine, double *fine, const double *coarse_new,
+                 const double *coarse_old);
+
+/* Total mass sum_ij rho_ij dx dy of `state` (synchronises). */
+int nrxx_mass(nrxx_ctx *ctx, int level, const double *state, double *mass_out);
+
+/* One NMG iteration NMG_K(f, 0) of Alg. 2 on the finest-level `state`
+ * (gamma recursive calls, s1/s2 smoothing, s3 coarsest steps), followed by
+ * the mass correction of Sec. 4 when mass0 > 0.  If norm_out != NULL, writes
+ * ||R(f)|| of the result (eq. (28)) and synchronises. */
+int nrxx_fas_vcycle(nrxx_ctx *ctx, double *state, double *norm_out);
+
+/* NMG solver of Sec. 3.2.3: repeat nrxx_fas_vcycle until
+ * ||R(f)|| <= tol * ref_norm (eq. (28)); ref_norm <= 0 means the norm of the
+ * input state.  Writes the number of cycles to *cycles_out and, if hist_out is
+ * non-NULL (max_cycles + 1 doubles), the norm history (entry 0 = input).
+ * Returns NRXX_OK on convergence, NRXX_EMAXIT if max_cycles was reached. */
+int nrxx_solve(nrxx_ctx *ctx, double *state, double tol, int max_cycles, double ref_norm,
+               int *cycles_out, double *hist_out);
+
+/* Cumulative device time (ms, from HIP events) spent in sweep kernels and the
+ * number of cell updates they made since the context was created or last
+ * reset; `reset` != 0 zeroes both after reading.  Synchronises. */
+int nrxx_sweep_stats(nrxx_ctx *ctx, double *ms_out, double *cell_updates_out, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

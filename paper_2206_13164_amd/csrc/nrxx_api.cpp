@@ -1,0 +1,450 @@
+// nrxx_api.cpp -- host side of the C ABI declared in include/nrxx.h: the
+// context, the level hierarchy of Sec. 3.2.2, the V-cycle of Alg. 2, the
+// mass correction of Sec. 4 and the solver loop of Sec. 3.2.3.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/nrxx.h"
+#include "nrxx_internal.hpp"
+
+using namespace nrxx;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+// Largest root of He_n: largest eigenvalue of the symmetric tridiagonal
+// (Jacobi) matrix of the probabilists' Hermite recurrence (off-diagonal
+// sqrt(k)), by Sturm-sequence bisection.
+double largest_hermite_root(int n) {
+  if (n <= 1) return 0.0;
+  auto count_below = [n](double x) {
+    int cnt = 0;
+    double d = -x;
+    if (d < 0) ++cnt;
+    for (int k = 1; k < n; ++k) {
+      if (d == 0.0) d = 1e-300;
+      d = -x - (double)k / d;
+      if (d < 0) ++cnt;
+    }
+    return cnt;
+  };
+  double lo = 0.0, hi = 2.0 * sqrt((double)n) + 2.0;
+  for (int it = 0; it < 200 && hi - lo > 0.0; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (mid == lo || mid == hi) break;
+    if (count_below(mid) >= n) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// J^-_{k0}(0) / k!: entering half-range of a wall Maxwellian at rest along
+// the normal, (2 pi)^-1/2 int_{-inf}^0 He_k(w) w e^{-w^2/2} dw / k!.
+// int_{-inf}^0 w He_k(w) e^{-w^2/2} = int_{-inf}^0 (He_{k+1} + k He_{k-1}) e^{-w^2/2},
+// and int_{-inf}^0 He_m e^{-w^2/2} = (-1)^m int_0^inf He_m e^{-w^2/2}, with
+// int_0^inf He_0 = sqrt(pi/2) and int_0^inf He_m = He_{m-1}(0) for m >= 1.
+void wall_entering_constants(int M, double *out) {
+  std::vector<double> h0(M + 3);  // He_m(0)
+  h0[0] = 1.0;
+  h0[1] = 0.0;
+  for (int m = 1; m + 1 < (int)h0.size(); ++m) h0[m + 1] = -m * h0[m - 1];
+  auto neg_half = [&](int m) {  // (2 pi)^-1/2 int_{-inf}^0 He_m e^{-w^2/2}
+    double pos = m == 0 ? 0.5 : h0[m - 1] / sqrt(2.0 * M_PI);
+    return (m % 2 == 0) ? pos : -pos;
+  };
+  double fact = 1.0;
+  for (int k = 0; k <= M; ++k) {
+    if (k > 0) fact *= k;
+    double v = neg_half(k + 1) + (k > 0 ? k * neg_half(k - 1) : 0.0);
+    out[k] = v / fact;
+  }
+}
+
+}  // namespace
+
+struct nrxx_ctx {
+  nrxx_problem P;
+  hipStream_t stream = nullptr;
+  int M = 0, stride = 0, L = 0;
+  std::vector<LevelArgs> lv;
+  // per level k: Rbar (k < L-1); fbar, ftil, rhs, RH (k >= 1)
+  std::vector<double *> Rbar, fbar, ftil, rhs, RH;
+  double *partial = nullptr;  // per-cell scalars of the finest level
+  double *dscal = nullptr;    // device scalars
+  double *hscal = nullptr;    // pinned host copies
+  int *derr = nullptr;
+  std::string err;
+  struct Timed { hipEvent_t a, b; double cells; };
+  std::vector<Timed> timed;
+  double sweep_ms = 0.0, sweep_cells = 0.0;
+};
+
+namespace {
+
+int fail(nrxx_ctx *c, int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  else g_create_error = buf;
+  return code;
+}
+
+int hipchk(nrxx_ctx *c, hipError_t e, const char *what) {
+  if (e == hipSuccess) return NRXX_OK;
+  return fail(c, NRXX_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define CHK(expr)                                   \
+  do {                                              \
+    int rc_ = hipchk(c, (expr), #expr);             \
+    if (rc_) return rc_;                            \
+  } while (0)
+
+bool level_ok(const nrxx_ctx *c, int level) { return c && level >= 0 && level < c->L; }
+
+size_t level_doubles(const nrxx_ctx *c, int k) {
+  return (size_t)c->lv[k].nx * c->lv[k].ny * c->stride;
+}
+
+// Read and clear the device error word; map it to a status.
+int check_device(nrxx_ctx *c) {
+  CHK(hipMemcpyAsync(c->hscal + 7, c->derr, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  CHK(hipStreamSynchronize(c->stream));
+  int e;
+  memcpy(&e, c->hscal + 7, sizeof(int));
+  if (e & 1) {
+    CHK(hipMemsetAsync(c->derr, 0, sizeof(int), c->stream));
+    return fail(c, NRXX_ENONPHYS, "non-physical state (rho <= 0 or theta <= 0) in an update");
+  }
+  return NRXX_OK;
+}
+
+int sweep_impl(nrxx_ctx *c, int level, double *st, const double *rhs, int mask, int nsteps) {
+  const LevelArgs &A = c->lv[level];
+  nrxx_ctx::Timed tm;
+  CHK(hipEventCreate(&tm.a));
+  CHK(hipEventCreate(&tm.b));
+  CHK(hipEventRecord(tm.a, c->stream));
+  int ndir = 0;
+  for (int s = 0; s < nsteps; ++s)
+    for (int k = 0; k < 4; ++k) {
+      if (!(mask & (1 << k))) continue;
+      ++ndir;
+      for (int t = 0; t <= A.nx + A.ny - 2; ++t)
+        CHK(launch_sweep_diag(c->M, A, st, rhs, k, t, c->derr, c->stream));
+    }
+  CHK(hipEventRecord(tm.b, c->stream));
+  tm.cells = (double)ndir * A.nx * A.ny;
+  c->timed.push_back(tm);
+  if (c->timed.size() > 4096) {  // fold finished timings
+    CHK(hipEventSynchronize(c->timed.back().b));
+    for (auto &x : c->timed) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, x.a, x.b);
+      c->sweep_ms += ms;
+      c->sweep_cells += x.cells;
+      (void)hipEventDestroy(x.a);
+      (void)hipEventDestroy(x.b);
+    }
+    c->timed.clear();
+  }
+  return NRXX_OK;
+}
+
+int residual_impl(nrxx_ctx *c, int level, const double *st, const double *rhs, double *out,
+                  double *norm_out) {
+  const LevelArgs &A = c->lv[level];
+  CHK(launch_residual(c->M, A, st, rhs, nullptr, out, norm_out ? c->partial : nullptr, 0, c->stream));
+  if (norm_out) {
+    CHK(launch_cell_sum(A, c->partial, 1, 0, A.inv_area, c->dscal, c->stream));
+    CHK(hipMemcpyAsync(c->hscal, c->dscal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    CHK(hipStreamSynchronize(c->stream));
+    *norm_out = sqrt(c->hscal[0]);
+  }
+  return NRXX_OK;
+}
+
+int vcycle_impl(nrxx_ctx *c, int k, double *st, const double *rhs) {
+  const nrxx_problem &P = c->P;
+  if (k == c->L - 1) return sweep_impl(c, k, st, rhs, 15, P.s3);
+  int rc = sweep_impl(c, k, st, rhs, 15, P.s1);
+  if (rc) return rc;
+  const LevelArgs &A = c->lv[k];
+  CHK(launch_residual(c->M, A, st, rhs, nullptr, c->Rbar[k], nullptr, 0, c->stream));
+  CHK(launch_restrict(c->M, A, st, c->Rbar[k], c->fbar[k + 1], c->RH[k + 1], c->derr, c->stream));
+  CHK(launch_residual(c->M, c->lv[k + 1], c->fbar[k + 1], nullptr, c->RH[k + 1], c->rhs[k + 1],
+                      nullptr, 1, c->stream));
+  CHK(hipMemcpyAsync(c->ftil[k + 1], c->fbar[k + 1], level_doubles(c, k + 1) * sizeof(double),
+                     hipMemcpyDeviceToDevice, c->stream));
+  for (int g = 0; g < P.gamma; ++g) {
+    rc = vcycle_impl(c, k + 1, c->ftil[k + 1], c->rhs[k + 1]);
+    if (rc) return rc;
+  }
+  CHK(launch_correct(c->M, A, st, c->ftil[k + 1], c->fbar[k + 1], c->derr, c->stream));
+  return sweep_impl(c, k, st, rhs, 15, P.s2);
+}
+
+int mass_fix_impl(nrxx_ctx *c, double *st) {
+  if (!(c->P.mass0 > 0.0)) return NRXX_OK;
+  const LevelArgs &A = c->lv[0];
+  CHK(launch_cell_sum(A, st, c->stride, 3, A.ds, c->dscal + 1, c->stream));
+  CHK(launch_mass_scale(c->M, A, st, c->dscal + 1, c->P.mass0, c->stream));
+  return NRXX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t nrxx_record_stride(int32_t M) { return (M >= MMIN && M <= MMAX) ? record_stride(M) : -1; }
+
+int nrxx_create(const nrxx_problem *p, void *hip_stream, nrxx_ctx **out) {
+  if (!out) return fail(nullptr, NRXX_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!p) return fail(nullptr, NRXX_EINVAL, "problem is NULL");
+  const nrxx_problem &P = *p;
+  if (P.M < MMIN || P.M > MMAX) return fail(nullptr, NRXX_EINVAL, "M = %d outside [%d, %d]", P.M, MMIN, MMAX);
+  if (P.levels < 1 || P.levels > 16) return fail(nullptr, NRXX_EINVAL, "levels = %d", P.levels);
+  if (P.nx < 1 || P.ny < 1) return fail(nullptr, NRXX_EINVAL, "grid %d x %d", P.nx, P.ny);
+  const int f = 1 << (P.levels - 1);
+  if (P.nx % f || P.ny % f) return fail(nullptr, NRXX_EINVAL, "grid %d x %d not divisible by 2^(levels-1) = %d", P.nx, P.ny, f);
+  if (P.nx / f < 2 || P.ny / f < 2) return fail(nullptr, NRXX_EINVAL, "coarsest grid below 2 x 2");
+  if (P.collision != 0 && P.collision != 1) return fail(nullptr, NRXX_EINVAL, "collision = %d", P.collision);
+  if (P.order != 1 && P.order != 2) return fail(nullptr, NRXX_EINVAL, "order = %d", P.order);
+  if (P.limiter != 0 && P.limiter != 1) return fail(nullptr, NRXX_EINVAL, "limiter = %d", P.limiter);
+  if (!(P.lx > 0) || !(P.ly > 0) || !(P.Kn > 0) || !(P.cfl > 0) || !(P.beta > 0))
+    return fail(nullptr, NRXX_EINVAL, "lx, ly, Kn, cfl and beta must be positive");
+  for (int w = 0; w < 4; ++w)
+    if (!(P.wall_theta[w] > 0)) return fail(nullptr, NRXX_EINVAL, "wall_theta[%d] <= 0", w);
+  if (P.s1 < 0 || P.s2 < 0 || P.s3 < 0 || P.gamma < 1 || P.gamma > 2)
+    return fail(nullptr, NRXX_EINVAL, "bad smoothing steps or gamma");
+  if (P.precision != 0) return fail(nullptr, NRXX_EINVAL, "precision = %d not supported", P.precision);
+  if ((long long)P.nx * P.ny > (1LL << 26)) return fail(nullptr, NRXX_EINVAL, "grid too large");
+
+  nrxx_ctx *c = new nrxx_ctx();
+  c->P = P;
+  c->stream = (hipStream_t)hip_stream;
+  c->M = P.M;
+  c->stride = record_stride(P.M);
+  c->L = P.levels;
+  double jm[MMAX + 1] = {0};
+  wall_entering_constants(P.M, jm);
+  const double C = largest_hermite_root(P.M + 1);
+  for (int k = 0; k < c->L; ++k) {
+    LevelArgs A{};
+    A.nx = P.nx >> k;
+    A.ny = P.ny >> k;
+    A.stride = c->stride;
+    A.collision = P.collision;
+    A.order = P.order;
+    A.limiter = P.limiter;
+    A.dx = P.lx / A.nx;
+    A.dy = P.ly / A.ny;
+    A.ds = A.dx * A.dy;
+    A.inv_area = 1.0 / (P.lx * P.ly);
+    A.Kn = P.Kn;
+    A.Pr = P.Pr;
+    A.omega = P.omega;
+    A.beta = P.beta;
+    A.cfl = P.cfl;
+    A.nu_cap = P.nu_dt_cap;
+    A.C = C;
+    for (int w = 0; w < 4; ++w) {
+      A.wall_u[w] = P.wall_u[w];
+      A.wall_th[w] = P.wall_theta[w];
+    }
+    for (int q = 0; q <= MMAX; ++q) A.jminus[q] = jm[q];
+    c->lv.push_back(A);
+  }
+  c->Rbar.assign(c->L, nullptr);
+  c->fbar.assign(c->L, nullptr);
+  c->ftil.assign(c->L, nullptr);
+  c->rhs.assign(c->L, nullptr);
+  c->RH.assign(c->L, nullptr);
+  auto alloc = [&](double **ptr, size_t n) {
+    return hipMalloc((void **)ptr, n * sizeof(double)) == hipSuccess;
+  };
+  bool ok = true;
+  for (int k = 0; k < c->L && ok; ++k) {
+    const size_t n = level_doubles(c, k);
+    if (k < c->L - 1) ok = ok && alloc(&c->Rbar[k], n);
+    if (k >= 1) ok = ok && alloc(&c->fbar[k], n) && alloc(&c->ftil[k], n) && alloc(&c->rhs[k], n) && alloc(&c->RH[k], n);
+  }
+  ok = ok && alloc(&c->partial, (size_t)P.nx * P.ny) && alloc(&c->dscal, 16);
+  ok = ok && hipMalloc((void **)&c->derr, sizeof(int)) == hipSuccess;
+  ok = ok && hipHostMalloc((void **)&c->hscal, 16 * sizeof(double), hipHostMallocDefault) == hipSuccess;
+  if (!ok) {
+    nrxx_destroy(c);
+    return fail(nullptr, NRXX_ENOMEM, "device allocation failed");
+  }
+  if (hipMemsetAsync(c->derr, 0, sizeof(int), c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    nrxx_destroy(c);
+    return fail(nullptr, NRXX_EHIP, "stream unusable");
+  }
+  *out = c;
+  return NRXX_OK;
+}
+
+int nrxx_destroy(nrxx_ctx *c) {
+  if (!c) return NRXX_OK;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto &x : c->timed) {
+    (void)hipEventDestroy(x.a);
+    (void)hipEventDestroy(x.b);
+  }
+  for (auto *v : {&c->Rbar, &c->fbar, &c->ftil, &c->rhs, &c->RH})
+    for (double *p : *v)
+      if (p) (void)hipFree(p);
+  if (c->partial) (void)hipFree(c->partial);
+  if (c->dscal) (void)hipFree(c->dscal);
+  if (c->derr) (void)hipFree(c->derr);
+  if (c->hscal) (void)hipHostFree(c->hscal);
+  delete c;
+  return NRXX_OK;
+}
+
+const char *nrxx_last_error(const nrxx_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int nrxx_level_shape(const nrxx_ctx *c, int level, int32_t *nx, int32_t *ny) {
+  if (!level_ok(c, level) || !nx || !ny) return NRXX_EINVAL;
+  *nx = c->lv[level].nx;
+  *ny = c->lv[level].ny;
+  return NRXX_OK;
+}
+
+int nrxx_init_maxwellian(nrxx_ctx *c, int level, double *state, double rho, double u1, double u2,
+                         double theta) {
+  if (!c) return NRXX_EINVAL;
+  if (!level_ok(c, level) || !state) return fail(c, NRXX_EINVAL, "bad level or NULL state");
+  if (!(rho > 0) || !(theta > 0)) return fail(c, NRXX_EINVAL, "rho and theta must be positive");
+  CHK(launch_init_maxwellian(c->M, c->lv[level], state, rho, u1, u2, theta, c->stream));
+  return NRXX_OK;
+}
+
+int nrxx_residual(nrxx_ctx *c, int level, const double *state, const double *rhs, double *R_out,
+                  double *norm_out) {
+  if (!c) return NRXX_EINVAL;
+  if (!level_ok(c, level) || !state) return fail(c, NRXX_EINVAL, "bad level or NULL state");
+  int rc = residual_impl(c, level, state, rhs, R_out, norm_out);
+  if (rc) return rc;
+  if (norm_out && !isfinite(*norm_out)) return fail(c, NRXX_EDIVERGED, "residual norm not finite");
+  return NRXX_OK;
+}
+
+int nrxx_sweep(nrxx_ctx *c, int level, double *state, const double *rhs, int dir_mask, int nsteps) {
+  if (!c) return NRXX_EINVAL;
+  if (!level_ok(c, level) || !state) return fail(c, NRXX_EINVAL, "bad level or NULL state");
+  if (dir_mask < 0 || dir_mask > 15 || nsteps < 0) return fail(c, NRXX_EINVAL, "bad dir_mask or nsteps");
+  return sweep_impl(c, level, state, rhs, dir_mask, nsteps);
+}
+
+int nrxx_restrict(nrxx_ctx *c, int level_fine, const double *fine, const double *fineR,
+                  double *coarse, double *coarseR) {
+  if (!c) return NRXX_EINVAL;
+  if (!level_ok(c, level_fine) || level_fine + 1 >= c->L || !fine || !coarse)
+    return fail(c, NRXX_EINVAL, "bad level or NULL buffer");
+  const double *fr = (fineR && coarseR) ? fineR : nullptr;
+  CHK(launch_restrict(c->M, c->lv[level_fine], fine, fr, coarse, fr ? coarseR : nullptr, c->derr, c->stream));
+  return NRXX_OK;
+}
+
+int nrxx_fas_rhs(nrxx_ctx *c, int level_coarse, const double *coarse, const double *coarseR,
+                 double *rhs) {
+  if (!c) return NRXX_EINVAL;
+  if (!level_ok(c, level_coarse) || !coarse || !coarseR || !rhs)
+    return fail(c, NRXX_EINVAL, "bad level or NULL buffer");
+  CHK(launch_residual(c->M, c->lv[level_coarse], coarse, nullptr, coarseR, rhs, nullptr, 1, c->stream));
+  return NRXX_OK;
+}
+
+int nrxx_correct(nrxx_ctx *c, int level_fine, double *fine, const double *coarse_new,
+                 const double *coarse_old) {
+  if (!c) return NRXX_EINVAL;
+  if (!level_ok(c, level_fine) || level_fine + 1 >= c->L || !fine || !coarse_new || !coarse_old)
+    return fail(c, NRXX_EINVAL, "bad level or NULL buffer");
+  CHK(launch_correct(c->M, c->lv[level_fine], fine, coarse_new, coarse_old, c->derr, c->stream));
+  return NRXX_OK;
+}
+
+int nrxx_mass(nrxx_ctx *c, int level, const double *state, double *mass_out) {
+  if (!c) return NRXX_EINVAL;
+  if (!level_ok(c, level) || !state || !mass_out) return fail(c, NRXX_EINVAL, "bad argument");
+  const LevelArgs &A = c->lv[level];
+  CHK(launch_cell_sum(A, state, c->stride, 3, A.ds, c->dscal + 2, c->stream));
+  CHK(hipMemcpyAsync(c->hscal + 2, c->dscal + 2, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  CHK(hipStreamSynchronize(c->stream));
+  *mass_out = c->hscal[2];
+  return NRXX_OK;
+}
+
+int nrxx_fas_vcycle(nrxx_ctx *c, double *state, double *norm_out) {
+  if (!c) return NRXX_EINVAL;
+  if (!state) return fail(c, NRXX_EINVAL, "NULL state");
+  int rc = vcycle_impl(c, 0, state, nullptr);
+  if (rc) return rc;
+  rc = mass_fix_impl(c, state);
+  if (rc) return rc;
+  if (norm_out) {
+    rc = residual_impl(c, 0, state, nullptr, nullptr, norm_out);
+    if (rc) return rc;
+    rc = check_device(c);
+    if (rc) return rc;
+    if (!isfinite(*norm_out)) return fail(c, NRXX_EDIVERGED, "residual norm not finite");
+  }
+  return NRXX_OK;
+}
+
+int nrxx_solve(nrxx_ctx *c, double *state, double tol, int max_cycles, double ref_norm,
+               int *cycles_out, double *hist_out) {
+  if (!c) return NRXX_EINVAL;
+  if (!state || !cycles_out || max_cycles < 0 || !(tol >= 0))
+    return fail(c, NRXX_EINVAL, "bad argument");
+  double nrm;
+  int rc = residual_impl(c, 0, state, nullptr, nullptr, &nrm);
+  if (rc) return rc;
+  if (!(ref_norm > 0)) ref_norm = nrm;
+  if (hist_out) hist_out[0] = nrm;
+  int n = 0;
+  *cycles_out = 0;
+  while (n < max_cycles && !(nrm <= tol * ref_norm)) {
+    rc = nrxx_fas_vcycle(c, state, &nrm);
+    if (rc) {
+      *cycles_out = n;
+      return rc;
+    }
+    ++n;
+    *cycles_out = n;
+    if (hist_out) hist_out[n] = nrm;
+  }
+  return nrm <= tol * ref_norm ? NRXX_OK : NRXX_EMAXIT;
+}
+
+int nrxx_sweep_stats(nrxx_ctx *c, double *ms_out, double *cells_out, int reset) {
+  if (!c) return NRXX_EINVAL;
+  CHK(hipStreamSynchronize(c->stream));
+  for (auto &x : c->timed) {
+    float ms = 0.f;
+    CHK(hipEventElapsedTime(&ms, x.a, x.b));
+    c->sweep_ms += ms;
+    c->sweep_cells += x.cells;
+    (void)hipEventDestroy(x.a);
+    (void)hipEventDestroy(x.b);
+  }
+  c->timed.clear();
+  if (ms_out) *ms_out = c->sweep_ms;
+  if (cells_out) *cells_out = c->sweep_cells;
+  if (reset) c->sweep_ms = c->sweep_cells = 0.0;
+  return NRXX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,44 @@
+// nrxx_internal.hpp -- declarations shared by the HIP kernels and the host
+// side of the C ABI.  Not part of the public interface (include/nrxx.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nrxx {
+
+constexpr int MMIN = 3;
+constexpr int MMAX = 8;
+
+__host__ __device__ constexpr int nalpha(int M) { return (M + 1) * (M + 2) * (M + 3) / 6; }
+__host__ __device__ constexpr int record_stride(int M) { return (nalpha(M) + 3 + 7) / 8 * 8; }
+
+// Per-level constants handed to every kernel by value.
+struct LevelArgs {
+  int nx, ny, stride;
+  int collision, order, limiter;
+  double dx, dy, ds, inv_area;  // cell size, cell area, 1 / (lx ly)
+  double Kn, Pr, omega, beta, cfl, nu_cap, C;  // C = largest root of He_{M+1}
+  double wall_u[4], wall_th[4];                // S, E, N, W
+  double jminus[MMAX + 1];                     // J^-_{k0}(0) / k!, entering wall half-range
+};
+
+// Launchers (host functions defined in nrxx_kernels.hip).  All enqueue on
+// `s` and return hipSuccess or the launch error.
+hipError_t launch_sweep_diag(int M, const LevelArgs &A, double *st, const double *rhs, int dir,
+                             int t, int *err, hipStream_t s);
+hipError_t launch_residual(int M, const LevelArgs &A, const double *st, const double *rhs,
+                           const double *Radd, double *out, double *norm_part, int mode,
+                           hipStream_t s);
+hipError_t launch_restrict(int M, const LevelArgs &Afine, const double *fine, const double *fineR,
+                           double *coarse, double *coarseR, int *err, hipStream_t s);
+hipError_t launch_correct(int M, const LevelArgs &Afine, double *fine, const double *cnew,
+                          const double *cold, int *err, hipStream_t s);
+hipError_t launch_init_maxwellian(int M, const LevelArgs &A, double *st, double rho, double u1,
+                                  double u2, double th, hipStream_t s);
+hipError_t launch_cell_sum(const LevelArgs &A, const double *src, int src_stride, int src_offset,
+                           double scale, double *dst, hipStream_t s);
+hipError_t launch_mass_scale(int M, const LevelArgs &A, double *st, const double *mass,
+                             double mass0, hipStream_t s);
+
+}  // namespace nrxx

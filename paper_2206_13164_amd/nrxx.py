@@ -1,0 +1,210 @@
+"""Python binding of ``libnrxx.so`` (the C ABI of ``include/nrxx.h``).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch provides device memory and the stream.  Importing works without a
+GPU; creating a context needs the built library and a GPU, and fails loudly
+otherwise (there is no fallback).
+
+Device state tensors have shape ``(ny, nx, record_stride(M))`` and dtype
+float64; record layout ``[u1, u2, theta, f_0 .. f_{N-1}, padding]``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnrxx.so")
+
+NRXX_OK, NRXX_EINVAL, NRXX_ENONPHYS, NRXX_EDIVERGED = 0, -1, -2, -3
+NRXX_ENOMEM, NRXX_EHIP, NRXX_EMAXIT = -4, -5, -6
+STATUS = {0: "NRXX_OK", -1: "NRXX_EINVAL", -2: "NRXX_ENONPHYS", -3: "NRXX_EDIVERGED",
+          -4: "NRXX_ENOMEM", -5: "NRXX_EHIP", -6: "NRXX_EMAXIT"}
+
+c_int, c_double, c_void_p = ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("nx", c_int), ("ny", c_int), ("lx", c_double), ("ly", c_double),
+        ("M", c_int), ("collision", c_int),
+        ("Pr", c_double), ("Kn", c_double), ("omega", c_double), ("beta", c_double),
+        ("order", c_int), ("limiter", c_int), ("cfl", c_double), ("nu_dt_cap", c_double),
+        ("wall_u", c_double * 4), ("wall_theta", c_double * 4),
+        ("levels", c_int), ("s1", c_int), ("s2", c_int), ("s3", c_int), ("gamma", c_int),
+        ("mass0", c_double), ("precision", c_int), ("schedule", c_int),
+    ]
+
+
+EXPORTS = {
+    "nrxx_record_stride": (c_int, [c_int]),
+    "nrxx_create": (c_int, [ctypes.POINTER(Problem), c_void_p, ctypes.POINTER(c_void_p)]),
+    "nrxx_destroy": (c_int, [c_void_p]),
+    "nrxx_last_error": (ctypes.c_char_p, [c_void_p]),
+    "nrxx_level_shape": (c_int, [c_void_p, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
+    "nrxx_init_maxwellian": (c_int, [c_void_p, c_int, c_void_p, c_double, c_double, c_double, c_double]),
+    "nrxx_residual": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double)]),
+    "nrxx_sweep": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_int, c_int]),
+    "nrxx_restrict": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "nrxx_fas_rhs": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
+    "nrxx_correct": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
+    "nrxx_mass": (c_int, [c_void_p, c_int, c_void_p, ctypes.POINTER(c_double)]),
+    "nrxx_fas_vcycle": (c_int, [c_void_p, c_void_p, ctypes.POINTER(c_double)]),
+    "nrxx_solve": (c_int, [c_void_p, c_void_p, c_double, c_int, c_double, ctypes.POINTER(c_int),
+                           c_void_p]),
+    "nrxx_sweep_stats": (c_int, [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double), c_int]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libnrxx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2206_13164_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class NrxxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def record_stride(M: int) -> int:
+    return load().nrxx_record_stride(M)
+
+
+def problem(spec) -> Problem:
+    p = Problem()
+    for name, _ in Problem._fields_:
+        if name == "schedule":
+            p.schedule = int(spec.get("schedule", 0))
+            continue
+        v = spec[name]
+        if name in ("wall_u", "wall_theta"):
+            getattr(p, name)[:] = [float(x) for x in v]
+        else:
+            setattr(p, name, v)
+    return p
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return c_void_p(t.data_ptr())
+
+
+class Context:
+    """Owns an nrxx_ctx.  Tensors passed in must be float64 CUDA tensors laid
+    out as (ny, nx, record_stride(M)) for the level they belong to."""
+
+    def __init__(self, spec, stream=None):
+        import torch
+        self.torch = torch
+        L = load()
+        self.spec = dict(spec)
+        self.M = int(spec["M"])
+        self.stride = record_stride(self.M)
+        self.P = problem(spec)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = c_void_p()
+        rc = L.nrxx_create(ctypes.byref(self.P), c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if rc != NRXX_OK:
+            raise NrxxError(rc, L.nrxx_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().nrxx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc, allow=()):
+        if rc != NRXX_OK and rc not in allow:
+            raise NrxxError(rc, load().nrxx_last_error(self.h).decode())
+        return rc
+
+    # -- helpers -----------------------------------------------------------
+    def level_shape(self, level):
+        nx, ny = c_int(), c_int()
+        self._chk(load().nrxx_level_shape(self.h, level, ctypes.byref(nx), ctypes.byref(ny)))
+        return nx.value, ny.value
+
+    def empty(self, level=0):
+        nx, ny = self.level_shape(level)
+        return self.torch.zeros((ny, nx, self.stride), dtype=self.torch.float64, device="cuda")
+
+    def to_device(self, rec: np.ndarray):
+        """(ny, nx, N+3) host records -> padded device tensor."""
+        ny, nx, r = rec.shape
+        t = self.torch.zeros((ny, nx, self.stride), dtype=self.torch.float64)
+        t[..., :r] = self.torch.from_numpy(np.ascontiguousarray(rec))
+        return t.to("cuda")
+
+    @staticmethod
+    def to_host(t, nrec: int) -> np.ndarray:
+        return t[..., :nrec].detach().cpu().numpy().copy()
+
+    # -- C ABI -------------------------------------------------------------
+    def init_maxwellian(self, state, level=0, rho=1.0, u=(0.0, 0.0), theta=1.0):
+        self._chk(load().nrxx_init_maxwellian(self.h, level, _ptr(state), rho, u[0], u[1], theta))
+
+    def residual(self, state, level=0, rhs=None, out=None, want_norm=True):
+        nrm = c_double()
+        self._chk(load().nrxx_residual(self.h, level, _ptr(state), _ptr(rhs), _ptr(out),
+                                       ctypes.byref(nrm) if want_norm else None))
+        return nrm.value if want_norm else None
+
+    def sweep(self, state, level=0, rhs=None, dir_mask=15, nsteps=1):
+        self._chk(load().nrxx_sweep(self.h, level, _ptr(state), _ptr(rhs), dir_mask, nsteps))
+
+    def restrict(self, fine, level_fine=0, fineR=None, coarse=None, coarseR=None):
+        self._chk(load().nrxx_restrict(self.h, level_fine, _ptr(fine), _ptr(fineR), _ptr(coarse),
+                                       _ptr(coarseR)))
+
+    def fas_rhs(self, coarse, coarseR, rhs, level_coarse):
+        self._chk(load().nrxx_fas_rhs(self.h, level_coarse, _ptr(coarse), _ptr(coarseR), _ptr(rhs)))
+
+    def correct(self, fine, coarse_new, coarse_old, level_fine=0):
+        self._chk(load().nrxx_correct(self.h, level_fine, _ptr(fine), _ptr(coarse_new), _ptr(coarse_old)))
+
+    def mass(self, state, level=0):
+        m = c_double()
+        self._chk(load().nrxx_mass(self.h, level, _ptr(state), ctypes.byref(m)))
+        return m.value
+
+    def fas_vcycle(self, state, want_norm=True):
+        nrm = c_double()
+        self._chk(load().nrxx_fas_vcycle(self.h, _ptr(state), ctypes.byref(nrm) if want_norm else None))
+        return nrm.value if want_norm else None
+
+    def solve(self, state, tol, max_cycles, ref_norm=0.0):
+        cyc = c_int()
+        hist = np.zeros(max_cycles + 1)
+        rc = load().nrxx_solve(self.h, _ptr(state), tol, max_cycles, ref_norm, ctypes.byref(cyc),
+                               hist.ctypes.data_as(c_void_p))
+        self._chk(rc, allow=(NRXX_EMAXIT,))
+        return rc, cyc.value, hist[: cyc.value + 1]
+
+    def sweep_stats(self, reset=False):
+        ms, cells = c_double(), c_double()
+        self._chk(load().nrxx_sweep_stats(self.h, ctypes.byref(ms), ctypes.byref(cells), int(reset)))
+        return ms.value, cells.value

@@ -1,0 +1,61 @@
+"""The C-ABI library loads, exports every symbol include/nrxx.h declares, and
+validates arguments on the host (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2206_13164_amd import inputs as I
+from paper_2206_13164_amd import nrxx as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "nrxx.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nrxx_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    decl = declared_functions()
+    assert "nrxx_residual" in decl and "nrxx_sweep" in decl
+    assert "nrxx_fas_vcycle" in decl and "nrxx_solve" in decl
+    assert set(decl) == set(N.EXPORTS), set(decl) ^ set(N.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = N.load()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_record_stride():
+    for M in range(3, 9):
+        s = N.record_stride(M)
+        assert s >= I.nalpha(M) + 3 and s % 8 == 0 and s - (I.nalpha(M) + 3) < 8
+    assert N.record_stride(2) == -1 and N.record_stride(9) == -1
+
+
+@pytest.mark.parametrize("bad", [
+    dict(M=2), dict(M=9), dict(nx=31), dict(levels=6), dict(order=3), dict(collision=2),
+    dict(Kn=0.0), dict(wall_theta=[1.0, 0.0, 1.0, 1.0]), dict(gamma=0), dict(precision=7),
+    dict(limiter=5), dict(nx=4, ny=4, levels=3),
+])
+def test_create_rejects_invalid_problems_before_touching_the_gpu(bad):
+    L = N.load()
+    P = N.problem(I.spec("lid32_bgk_m3", **bad))
+    h = ctypes.c_void_p(123)
+    rc = L.nrxx_create(ctypes.byref(P), None, ctypes.byref(h))
+    assert rc == N.NRXX_EINVAL
+    assert h.value is None
+    assert len(L.nrxx_last_error(None)) > 0
+
+
+def test_null_arguments():
+    L = N.load()
+    assert L.nrxx_create(None, None, None) == N.NRXX_EINVAL
+    assert L.nrxx_destroy(None) == N.NRXX_OK
+    assert L.nrxx_residual(None, 0, None, None, None, None) == N.NRXX_EINVAL
+    assert L.nrxx_solve(None, None, 1e-8, 1, 0.0, None, None) == N.NRXX_EINVAL

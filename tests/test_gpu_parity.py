@@ -1,0 +1,269 @@
+"""GPU parity: the HIP library, called through the C ABI, against the FP64
+oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+
+from gpu_common import TOL_CONVERGED, TOL_STEP, context, record_err, require_gpu, state_err
+from paper_2206_13164_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+# (M, collision, order, limiter): every kernel instantiation of the configs
+# plus the remaining orders of the template range
+CASES = [
+    (3, 0, 1, 0), (3, 1, 2, 0), (4, 1, 2, 1), (5, 1, 2, 0), (5, 0, 1, 0),
+    (6, 1, 1, 0), (7, 1, 2, 0), (8, 1, 2, 0), (8, 1, 1, 0),
+]
+
+
+def small_spec(M, collision, order, limiter, **kw):
+    d = dict(M=M, collision=collision, Pr=2.0 / 3.0 if collision else 1.0, order=order,
+             limiter=limiter, nx=12, ny=10, lx=1.0, ly=0.8, Kn=0.15, levels=2,
+             wall_u=[0.1, -0.15, 0.35, 0.05], wall_theta=[1.6, 1.0, 0.9, 1.2])
+    d.update(kw)
+    return I.spec(None, **d)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_residual_matches_oracle(orc, case):
+    require_gpu()
+    s = small_spec(*case)
+    P = orc.problem(s)
+    st = I.random_state(s, seed=11, amp=0.08)
+    rhs = I.random_rhs(s, 0, seed=12)
+    ctx = context(s)
+    dst = ctx.to_device(st)
+    for r in (None, rhs):
+        want, wn = orc.residual(P, 0, st, rhs=r)
+        out = ctx.empty(0)
+        gn = ctx.residual(dst, rhs=None if r is None else ctx.to_device(r), out=out)
+        got = ctx.to_host(out, st.shape[-1])
+        assert record_err(got, want) < TOL_STEP
+        assert abs(gn - wn) < TOL_STEP * wn
+    # odd alpha_3 coefficients are written as exact zeros
+    odd = I.alpha_list(s["M"])[:, 2] % 2 == 1
+    assert np.all(got[..., 3:][..., odd] == 0.0)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_sweep_matches_oracle(orc, case):
+    require_gpu()
+    s = small_spec(*case)
+    P = orc.problem(s)
+    ctx = context(s)
+    st0 = I.random_state(s, seed=5, amp=0.06)
+    for mask in (1, 2, 4, 8, 15):
+        want = st0.copy()
+        orc.sweep(P, 0, want, dir_mask=mask)
+        d = ctx.to_device(st0)
+        ctx.sweep(d, dir_mask=mask)
+        got = ctx.to_host(d, st0.shape[-1])
+        assert state_err(got, want, s["M"]) < TOL_STEP, mask
+
+
+@pytest.mark.parametrize("case", [(5, 1, 2, 0), (3, 0, 1, 0), (8, 1, 2, 0)])
+def test_coarse_sweep_with_rhs_matches_oracle(orc, case):
+    require_gpu()
+    s = small_spec(*case)
+    P = orc.problem(s)
+    ctx = context(s)
+    st = I.random_state(s, level=1, seed=21, amp=0.06)
+    rhs = I.random_rhs(s, 1, seed=22)
+    want = st.copy()
+    orc.sweep(P, 1, want, rhs=rhs, dir_mask=15, nsteps=2)
+    d = ctx.to_device(st)
+    ctx.sweep(d, level=1, rhs=ctx.to_device(rhs), dir_mask=15, nsteps=2)
+    assert state_err(ctx.to_host(d, st.shape[-1]), want, s["M"]) < TOL_STEP
+
+
+@pytest.mark.parametrize("case", [(5, 1, 2, 0), (3, 0, 1, 0), (8, 1, 2, 0)])
+def test_transfer_operators_match_oracle(orc, case):
+    require_gpu()
+    s = small_spec(*case)
+    P = orc.problem(s)
+    ctx = context(s)
+    st = I.random_state(s, seed=31, amp=0.08)
+    R, _ = orc.residual(P, 0, st)
+    cw, cRw = orc.restrict(P, 0, st, R)
+    c, cR = ctx.empty(1), ctx.empty(1)
+    ctx.restrict(ctx.to_device(st), 0, fineR=ctx.to_device(R), coarse=c, coarseR=cR)
+    nr = st.shape[-1]
+    assert state_err(ctx.to_host(c, nr), cw, s["M"]) < TOL_STEP
+    assert record_err(ctx.to_host(cR, nr), cRw) < TOL_STEP
+    # FAS right-hand side, eq. (22)
+    rw = orc.fas_rhs(P, 1, cw, cRw)
+    rhs = ctx.empty(1)
+    ctx.fas_rhs(ctx.to_device(cw), ctx.to_device(cRw), rhs, 1)
+    assert record_err(ctx.to_host(rhs, nr), rw) < TOL_STEP
+    # correction, eq. (26), with a perturbed coarse solution
+    cnew = cw.copy()
+    orc.sweep(P, 1, cnew, rhs=rw, nsteps=1)
+    fw = st.copy()
+    orc.correct(P, 0, fw, cnew, cw)
+    fd = ctx.to_device(st)
+    ctx.correct(fd, ctx.to_device(cnew), ctx.to_device(cw), 0)
+    assert state_err(ctx.to_host(fd, nr), fw, s["M"]) < TOL_STEP
+
+
+@pytest.mark.parametrize("name,kw", [
+    ("lid32_bgk_m3", {}),
+    ("lid128_shakhov_m5", dict(nx=32, ny=32, levels=3)),
+    ("heated256_shakhov_m8_kn02", dict(nx=16, ny=16, levels=2)),
+])
+def test_vcycle_matches_oracle(orc, name, kw):
+    require_gpu()
+    s = I.spec(name, **kw)
+    P = orc.problem(s)
+    ctx = context(s)
+    st = I.maxwellian_state(s)
+    d = ctx.to_device(st)
+    for _ in range(2):
+        orc.vcycle(P, st)
+        orc.mass_fix(P, st)
+        gn = ctx.fas_vcycle(d)
+        got = ctx.to_host(d, st.shape[-1])
+        assert state_err(got, st, s["M"]) < TOL_STEP
+    _, wn = orc.residual(P, 0, st)
+    assert abs(gn - wn) < 1e-10 * wn
+
+
+def test_converged_fields_match_oracle_config1(orc):
+    # config 1 solved to 1e-8 by the oracle; the GPU runs the same number of
+    # V-cycles from the same start
+    require_gpu()
+    s = I.spec("lid32_bgk_m3")
+    P = orc.problem(s)
+    orc.set_threads(8)
+    try:
+        st = I.maxwellian_state(s)
+        rc, cyc, hist = orc.solve(P, st, s["tol"], 60)
+    finally:
+        orc.set_threads(1)
+    assert rc == 0
+    ctx = context(s)
+    d = ctx.to_device(I.maxwellian_state(s))
+    ref = ctx.residual(d)
+    rcg, cg, hg = ctx.solve(d, 0.0, cyc, ref_norm=ref)
+    assert cg == cyc
+    got = ctx.to_host(d, st.shape[-1])
+    assert state_err(got, st, s["M"]) < TOL_CONVERGED
+    assert np.allclose(hg, hist, rtol=1e-8, atol=0)
+    # and the GPU's own stopping test agrees with the oracle's count
+    d2 = ctx.to_device(I.maxwellian_state(s))
+    rc2, c2, _ = ctx.solve(d2, s["tol"], 60)
+    assert rc2 == 0 and abs(c2 - cyc) <= 1
+
+
+def test_converged_fields_match_oracle_config2_reduced(orc):
+    # config-2 physics (Shakhov Pr 2/3, Kn 0.075, M = 5, 2nd order minmod,
+    # lid 0.5) on 32x32 with 3 levels, fixed cycle count
+    require_gpu()
+    s = I.spec("lid128_shakhov_m5", nx=32, ny=32, levels=3)
+    P = orc.problem(s)
+    st = I.maxwellian_state(s)
+    n = 12
+    orc.set_threads(8)
+    try:
+        _, r0 = orc.residual(P, 0, st)
+        rc, cyc, hist = orc.solve(P, st, 0.0, n, ref_norm=r0)
+    finally:
+        orc.set_threads(1)
+    ctx = context(s)
+    d = ctx.to_device(I.maxwellian_state(s))
+    ctx.solve(d, 0.0, n, ref_norm=r0)
+    assert state_err(ctx.to_host(d, st.shape[-1]), st, s["M"]) < TOL_CONVERGED
+
+
+@pytest.mark.parametrize("name", ["lid128_shakhov_m5", "heated256_shakhov_m8_kn005"])
+def test_full_size_residual_sampled(orc, name):
+    # full-size grid: GPU residual of a random state against the oracle's
+    # cell-by-cell residual at sampled cells (corners, walls, interior)
+    require_gpu()
+    s = I.spec(name)
+    P = orc.problem(s)
+    st = I.random_state(s, seed=3, amp=0.05)
+    ctx = context(s)
+    out = ctx.empty(0)
+    ctx.residual(ctx.to_device(st), out=out, want_norm=False)
+    got = ctx.to_host(out, st.shape[-1])
+    nx, ny = s["nx"], s["ny"]
+    rng = np.random.default_rng(0)
+    cells = [(0, 0), (nx - 1, 0), (0, ny - 1), (nx - 1, ny - 1), (1, 0), (0, 1), (nx - 2, ny - 1),
+             (nx // 2, 0), (nx - 1, ny // 2)] + [tuple(rng.integers(0, [nx, ny])) for _ in range(40)]
+    for (i, j) in cells:
+        want = -orc.cell_residual(P, 0, st, int(i), int(j))
+        g = got[j, i, 3:]
+        assert np.abs(g - want).max() <= TOL_STEP * max(np.abs(want).max(), 1e-300), (i, j)
+
+
+def test_full_size_sweep_config2(orc):
+    # one full fast-sweeping step at the config-2 size, every cell compared
+    # (oracle in its bit-identical wavefront order on all host threads)
+    require_gpu()
+    s = I.spec("lid128_shakhov_m5")
+    P = orc.problem(s)
+    st = I.random_state(s, seed=8, amp=0.05)
+    want = st.copy()
+    orc.set_threads(16)
+    try:
+        orc.sweep(P, 0, want, dir_mask=15, wavefront=True)
+    finally:
+        orc.set_threads(1)
+    ctx = context(s)
+    d = ctx.to_device(st)
+    ctx.sweep(d, dir_mask=15)
+    assert state_err(ctx.to_host(d, st.shape[-1]), want, s["M"]) < TOL_STEP
+
+
+def test_edge_cases(orc):
+    require_gpu()
+    from paper_2206_13164_amd import nrxx as N
+    # smallest grids: 2x2 single level, 4x2 two levels (coarsest 2x1 is refused)
+    for kw in (dict(nx=2, ny=2, levels=1), dict(nx=4, ny=8, levels=2), dict(nx=3, ny=5, levels=1)):
+        s = small_spec(5, 1, 2, 0, **kw)
+        P = orc.problem(s)
+        st = I.random_state(s, seed=2, amp=0.05)
+        ctx = context(s)
+        d = ctx.to_device(st)
+        want = st.copy()
+        orc.sweep(P, 0, want)
+        ctx.sweep(d)
+        assert state_err(ctx.to_host(d, st.shape[-1]), want, 5) < TOL_STEP
+    s = small_spec(3, 0, 1, 0)
+    ctx = context(s)
+    d = ctx.empty(0)
+    ctx.init_maxwellian(d, rho=1.0, theta=1.0)
+    with pytest.raises(N.NrxxError):
+        ctx.sweep(d, level=5)
+    with pytest.raises(N.NrxxError):
+        ctx.sweep(d, dir_mask=16)
+    # zero steps and an empty mask change nothing
+    before = d.clone()
+    ctx.sweep(d, nsteps=0)
+    ctx.sweep(d, dir_mask=0)
+    assert bool((before == d).all())
+    # a non-physical state is reported by the next synchronising call
+    st = I.maxwellian_state(s)
+    st[2, 3, 3] = -1.0
+    d = ctx.to_device(st)
+    with pytest.raises(N.NrxxError) as ei:
+        ctx.fas_vcycle(d)
+    assert ei.value.code == N.NRXX_ENONPHYS
+    # max_cycles reached
+    d = ctx.empty(0)
+    ctx.init_maxwellian(d)
+    rc, cyc, _ = ctx.solve(d, 1e-14, 2)
+    assert rc == N.NRXX_EMAXIT and cyc == 2
+
+
+def test_mass_and_init(orc):
+    require_gpu()
+    s = I.spec("lid32_bgk_m3")
+    P = orc.problem(s)
+    ctx = context(s)
+    d = ctx.empty(0)
+    ctx.init_maxwellian(d, rho=0.7, u=(0.1, -0.2), theta=1.3)
+    want = I.maxwellian_state(s, rho=0.7, u=(0.1, -0.2), theta=1.3)
+    assert np.array_equal(ctx.to_host(d, want.shape[-1]), want)
+    st = I.random_state(s, seed=4)
+    assert abs(ctx.mass(ctx.to_device(st)) - orc.mass(P, 0, st)) < 1e-14
