@@ -78,9 +78,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="lid128_shakhov_m5")
+    ap.add_argument("--workload", default="lid128_shakhov_m5_central")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-cycles", type=int, default=200)
+    ap.add_argument("--schedule", type=int, default=0,
+                    help="sweep schedule: 0 automatic, 1 per-diagonal launches, 2 persistent")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver's "
@@ -92,7 +94,7 @@ def main():
     from paper_2206_13164_amd import inputs as I
     from paper_2206_13164_amd import nrxx as N
 
-    spec = I.spec(args.workload)
+    spec = I.spec(args.workload, schedule=args.schedule)
     tol = spec["tol"]
     M = spec["M"]
     NA = math.comb(M + 3, 3)

@@ -87,7 +87,9 @@ typedef struct {
   int32_t gamma;          /* 1 = V-cycle, 2 = W-cycle */
   double mass0;           /* > 0: total mass restored after every cycle (Sec. 4); <= 0: off */
   int32_t precision;      /* 0 = FP64 throughout (the only value accepted) */
-  int32_t schedule;       /* sweep schedule: 0 = automatic, 1 = one launch per diagonal */
+  int32_t schedule;       /* sweep schedule: 0 = automatic (persistent where the grid's columns
+                             fit on the device at once), 1 = one launch per anti-diagonal,
+                             2 = persistent on every level (NRXX_EINVAL if impossible) */
 } nrxx_problem;
 
 /* Doubles per cell record for order M (N + 3 rounded up to a multiple of 8). */
@@ -109,6 +111,12 @@ const char *nrxx_last_error(const nrxx_ctx *ctx);
 
 /* Cells of `level` (0 = finest). */
 int nrxx_level_shape(const nrxx_ctx *ctx, int level, int32_t *nx, int32_t *ny);
+
+/* Sweep schedule used on `level`: 1 = one launch per anti-diagonal,
+ * 2 = persistent (one workgroup per grid column, cells of a column in sweep
+ * order, waits on the progress of neighbouring columns).  Both give the
+ * serial Gauss-Seidel result.  Negative: NRXX_EINVAL. */
+int nrxx_level_schedule(const nrxx_ctx *ctx, int level);
 
 /* Fill `state` (a level-`level` record array) with the global Maxwellian of
  * density rho, velocity (u1, u2) and temperature theta (Sec. 4.1). */

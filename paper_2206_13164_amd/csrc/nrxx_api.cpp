@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -79,6 +80,10 @@ struct nrxx_ctx {
   double *dscal = nullptr;    // device scalars
   double *hscal = nullptr;    // pinned host copies
   int *derr = nullptr;
+  int *dabort = nullptr;                 // abort flag of persistent sweeps
+  std::vector<int *> cnt;                // per level: column progress counters
+  std::vector<long long> pbase;          // per level: counter value at the next launch
+  std::vector<int> persist;              // per level: 1 = persistent sweeps
   std::string err;
   struct Timed { hipEvent_t a, b; double cells; };
   std::vector<Timed> timed;
@@ -121,6 +126,17 @@ int check_device(nrxx_ctx *c) {
   CHK(hipStreamSynchronize(c->stream));
   int e;
   memcpy(&e, c->hscal + 7, sizeof(int));
+  if (e & 4) {
+    // a persistent sweep gave up waiting: counters are inconsistent, reset
+    CHK(hipMemsetAsync(c->derr, 0, sizeof(int), c->stream));
+    CHK(hipMemsetAsync(c->dabort, 0, sizeof(int), c->stream));
+    for (int k = 0; k < c->L; ++k) {
+      CHK(hipMemsetAsync(c->cnt[k], 0, sizeof(int) * c->lv[k].nx, c->stream));
+      c->pbase[k] = 0;
+    }
+    CHK(hipStreamSynchronize(c->stream));
+    return fail(c, NRXX_EHIP, "persistent sweep timed out waiting for a neighbouring column");
+  }
   if (e & 1) {
     CHK(hipMemsetAsync(c->derr, 0, sizeof(int), c->stream));
     return fail(c, NRXX_ENONPHYS, "non-physical state (rho <= 0 or theta <= 0) in an update");
@@ -135,13 +151,30 @@ int sweep_impl(nrxx_ctx *c, int level, double *st, const double *rhs, int mask, 
   CHK(hipEventCreate(&tm.b));
   CHK(hipEventRecord(tm.a, c->stream));
   int ndir = 0;
+  std::vector<int> dirs;
   for (int s = 0; s < nsteps; ++s)
-    for (int k = 0; k < 4; ++k) {
-      if (!(mask & (1 << k))) continue;
-      ++ndir;
+    for (int k = 0; k < 4; ++k)
+      if (mask & (1 << k)) dirs.push_back(k);
+  ndir = (int)dirs.size();
+  if (c->persist[level]) {
+    // up to 16 directional sweeps per launch (2 bits per direction)
+    for (size_t s0 = 0; s0 < dirs.size(); s0 += 16) {
+      const int nsw = (int)std::min<size_t>(16, dirs.size() - s0);
+      unsigned bits = 0;
+      for (int q = 0; q < nsw; ++q) bits |= (unsigned)dirs[s0 + q] << (2 * q);
+      if (c->pbase[level] + (long long)nsw * A.ny > (1LL << 30)) {
+        CHK(hipMemsetAsync(c->cnt[level], 0, sizeof(int) * A.nx, c->stream));
+        c->pbase[level] = 0;
+      }
+      CHK(launch_sweep_persist(c->M, A, st, rhs, nsw, bits, c->cnt[level], (int)c->pbase[level],
+                               c->derr, c->dabort, 200000000ULL /* 2 s */, c->stream));
+      c->pbase[level] += (long long)nsw * A.ny;
+    }
+  } else {
+    for (int k : dirs)
       for (int t = 0; t <= A.nx + A.ny - 2; ++t)
         CHK(launch_sweep_diag(c->M, A, st, rhs, k, t, c->derr, c->stream));
-    }
+  }
   CHK(hipEventRecord(tm.b, c->stream));
   tm.cells = (double)ndir * A.nx * A.ny;
   c->timed.push_back(tm);
@@ -228,6 +261,7 @@ int nrxx_create(const nrxx_problem *p, void *hip_stream, nrxx_ctx **out) {
   if (P.s1 < 0 || P.s2 < 0 || P.s3 < 0 || P.gamma < 1 || P.gamma > 2)
     return fail(nullptr, NRXX_EINVAL, "bad smoothing steps or gamma");
   if (P.precision != 0) return fail(nullptr, NRXX_EINVAL, "precision = %d not supported", P.precision);
+  if (P.schedule < 0 || P.schedule > 2) return fail(nullptr, NRXX_EINVAL, "schedule = %d", P.schedule);
   if ((long long)P.nx * P.ny > (1LL << 26)) return fail(nullptr, NRXX_EINVAL, "grid too large");
 
   nrxx_ctx *c = new nrxx_ctx();
@@ -249,6 +283,8 @@ int nrxx_create(const nrxx_problem *p, void *hip_stream, nrxx_ctx **out) {
     A.limiter = P.limiter;
     A.dx = P.lx / A.nx;
     A.dy = P.ly / A.ny;
+    A.idx = 1.0 / A.dx;
+    A.idy = 1.0 / A.dy;
     A.ds = A.dx * A.dy;
     A.inv_area = 1.0 / (P.lx * P.ly);
     A.Kn = P.Kn;
@@ -281,15 +317,35 @@ int nrxx_create(const nrxx_problem *p, void *hip_stream, nrxx_ctx **out) {
   }
   ok = ok && alloc(&c->partial, (size_t)P.nx * P.ny) && alloc(&c->dscal, 16);
   ok = ok && hipMalloc((void **)&c->derr, sizeof(int)) == hipSuccess;
+  ok = ok && hipMalloc((void **)&c->dabort, sizeof(int)) == hipSuccess;
+  c->cnt.assign(c->L, nullptr);
+  c->pbase.assign(c->L, 0);
+  c->persist.assign(c->L, 0);
+  for (int k = 0; k < c->L && ok; ++k)
+    ok = hipMalloc((void **)&c->cnt[k], sizeof(int) * c->lv[k].nx) == hipSuccess;
   ok = ok && hipHostMalloc((void **)&c->hscal, 16 * sizeof(double), hipHostMallocDefault) == hipSuccess;
   if (!ok) {
     nrxx_destroy(c);
     return fail(nullptr, NRXX_ENOMEM, "device allocation failed");
   }
-  if (hipMemsetAsync(c->derr, 0, sizeof(int), c->stream) != hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess) {
+  bool zero_ok = hipMemsetAsync(c->derr, 0, sizeof(int), c->stream) == hipSuccess &&
+                 hipMemsetAsync(c->dabort, 0, sizeof(int), c->stream) == hipSuccess;
+  for (int k = 0; k < c->L && zero_ok; ++k)
+    zero_ok = hipMemsetAsync(c->cnt[k], 0, sizeof(int) * c->lv[k].nx, c->stream) == hipSuccess;
+  if (!zero_ok || hipStreamSynchronize(c->stream) != hipSuccess) {
     nrxx_destroy(c);
     return fail(nullptr, NRXX_EHIP, "stream unusable");
+  }
+  // sweep schedule per level: persistent (one workgroup per column, all
+  // resident at once) or one launch per anti-diagonal
+  const int maxcols = P.schedule == 1 ? 0 : persist_max_columns(P.M, P.order);
+  for (int k = 0; k < c->L; ++k) {
+    c->persist[k] = P.schedule != 1 && c->lv[k].nx <= maxcols;
+    if (P.schedule == 2 && !c->persist[k]) {
+      nrxx_destroy(c);
+      return fail(nullptr, NRXX_EINVAL, "persistent sweeps need %d resident workgroups, device holds %d",
+                  c->lv[k].nx, maxcols);
+    }
   }
   *out = c;
   return NRXX_OK;
@@ -308,6 +364,9 @@ int nrxx_destroy(nrxx_ctx *c) {
   if (c->partial) (void)hipFree(c->partial);
   if (c->dscal) (void)hipFree(c->dscal);
   if (c->derr) (void)hipFree(c->derr);
+  if (c->dabort) (void)hipFree(c->dabort);
+  for (int *p : c->cnt)
+    if (p) (void)hipFree(p);
   if (c->hscal) (void)hipHostFree(c->hscal);
   delete c;
   return NRXX_OK;
@@ -320,6 +379,11 @@ int nrxx_level_shape(const nrxx_ctx *c, int level, int32_t *nx, int32_t *ny) {
   *nx = c->lv[level].nx;
   *ny = c->lv[level].ny;
   return NRXX_OK;
+}
+
+int nrxx_level_schedule(const nrxx_ctx *c, int level) {
+  if (!level_ok(c, level)) return NRXX_EINVAL;
+  return c->persist[level] ? 2 : 1;
 }
 
 int nrxx_init_maxwellian(nrxx_ctx *c, int level, double *state, double rho, double u1, double u2,
@@ -337,7 +401,11 @@ int nrxx_residual(nrxx_ctx *c, int level, const double *state, const double *rhs
   if (!level_ok(c, level) || !state) return fail(c, NRXX_EINVAL, "bad level or NULL state");
   int rc = residual_impl(c, level, state, rhs, R_out, norm_out);
   if (rc) return rc;
-  if (norm_out && !isfinite(*norm_out)) return fail(c, NRXX_EDIVERGED, "residual norm not finite");
+  if (norm_out) {
+    rc = check_device(c);
+    if (rc) return rc;
+    if (!isfinite(*norm_out)) return fail(c, NRXX_EDIVERGED, "residual norm not finite");
+  }
   return NRXX_OK;
 }
 

@@ -17,7 +17,7 @@ __host__ __device__ constexpr int record_stride(int M) { return (nalpha(M) + 3 +
 struct LevelArgs {
   int nx, ny, stride;
   int collision, order, limiter;
-  double dx, dy, ds, inv_area;  // cell size, cell area, 1 / (lx ly)
+  double dx, dy, idx, idy, ds, inv_area;  // cell size, its inverse, cell area, 1 / (lx ly)
   double Kn, Pr, omega, beta, cfl, nu_cap, C;  // C = largest root of He_{M+1}
   double wall_u[4], wall_th[4];                // S, E, N, W
   double jminus[MMAX + 1];                     // J^-_{k0}(0) / k!, entering wall half-range
@@ -27,6 +27,16 @@ struct LevelArgs {
 // `s` and return hipSuccess or the launch error.
 hipError_t launch_sweep_diag(int M, const LevelArgs &A, double *st, const double *rhs, int dir,
                              int t, int *err, hipStream_t s);
+// Persistent sweeps: `nsweep` directions (2 bits each in dirs) in one launch,
+// one workgroup per grid column; cnt[nx] are monotone progress counters that
+// hold `base` for every column at launch; waits give up after `limit` ticks
+// of the 100 MHz wall clock and set *abort_flag and bit 2 of *err.
+hipError_t launch_sweep_persist(int M, const LevelArgs &A, double *st, const double *rhs,
+                                int nsweep, unsigned dirs, int *cnt, int base, int *err,
+                                int *abort_flag, unsigned long long limit, hipStream_t s);
+// Columns (workgroups) of the persistent sweep kernel that can be resident at
+// once on the current device (0 if unknown).
+int persist_max_columns(int M, int order);
 hipError_t launch_residual(int M, const LevelArgs &A, const double *st, const double *rhs,
                            const double *Radd, double *out, double *norm_part, int mode,
                            hipStream_t s);

@@ -3,14 +3,21 @@
 // evaluated per cell, the fast-sweeping cell update of Alg. 1, restriction
 // (eq. (24)-(25)), coarse-grid correction (eq. (26)) and reductions.
 //
-// Execution model: one 64-lane wavefront ("team") owns one cell.  Lanes run
-// over the expansion coefficients with even alpha_3 (the odd ones vanish
-// identically for this xi_3-even, two-dimensional problem), so a team holds
-// 13 / 34 / 95 coefficients at M = 3 / 5 / 8 in 1 or 2 registers per lane.
-// Coefficient vectors that lanes must read from each other live in LDS in a
-// dense "cube" (alpha_1, alpha_2, alpha_3 / 2) of (M+1) x (M+1) x (M/2+1)
-// doubles: every shift alpha -/+ k e_d of the Hermite algebra is then a
-// compile-time LDS offset folded into the ds_read instruction.
+// Execution model.  A cell is evaluated by a workgroup of NW wavefronts (a
+// "cell team").  The eight face-side items of the cell -- for each of the
+// faces E, W, N, S the half-flux of the cell's own face state and of the
+// neighbour's face state, each projected into the cell's basis (or, at a
+// wall, the wall flux) -- are spread over the wavefronts and run in parallel;
+// wavefront 0 then adds them up in a fixed order (independent of NW) with the
+// regularisation and collision terms and, in a sweep, re-expands the updated
+// cell in its new basis.
+// Within a wavefront, lanes run over the expansion coefficients with even
+// alpha_3 (the odd ones vanish identically for this xi_3-even, two-
+// dimensional problem): 13 / 34 / 95 coefficients at M = 3 / 5 / 8 in 1 or 2
+// registers per lane.  Coefficient vectors that lanes must read from each
+// other live in LDS in a dense "cube" (alpha_1, alpha_2, alpha_3 / 2) of
+// (M+1) x (M+1) x (M/2+1) doubles, so every shift alpha -/+ k e_d of the
+// Hermite algebra is a compile-time LDS offset.
 // Global memory holds cell records [u1, u2, theta, f_0 .. f_{N-1}] in the
 // graded order of the C ABI, one record per cell, row-major.
 #include <math.h>
@@ -74,14 +81,17 @@ constexpr CanonTab make_canon_tab() {
 }
 struct FactTab {
   double v[2 * MMAX + 4];
+  double inv[2 * MMAX + 4];
 };
 constexpr FactTab make_fact_tab() {
   FactTab t{};
   double f = 1.0;
   t.v[0] = 1.0;
+  t.inv[0] = 1.0;
   for (int n = 1; n < 2 * MMAX + 4; ++n) {
     f *= n;
     t.v[n] = f;
+    t.inv[n] = 1.0 / f;
   }
   return t;
 }
@@ -102,15 +112,39 @@ struct G {
   static constexpr int NE = neven(M);
   static constexpr int SL = (NE + WAVE - 1) / WAVE;  // even-alpha slots per lane
   static constexpr int SR = (NR + WAVE - 1) / WAVE;  // record entries per lane
+  static constexpr int SLOT = SL * WAVE;             // one per-slot buffer
   static constexpr int KOFF = 0;                     // K_n(a), n = 0 .. 2M+1
   static constexpr int JOFF = 2 * M + 2;             // J+_{kl}(a), (M+1)^2
   static constexpr int BOFF = JOFF + (M + 1) * (M + 1);  // broadcast slots
   static constexpr int MISC = BOFF + 16;
-  static constexpr int TEAM_LDS = 6 * CUBE + MISC;  // doubles per team
   // cube addresses of coefficients used by name
   static constexpr int E1 = 1, E2 = D1, XX = 2, YY = 2 * D1, ZZ = D2;
   static constexpr int X3 = 3, X1Y2 = 1 + 2 * D1, X1Z2 = 1 + D2;
   static constexpr int Y3 = 3 * D1, X2Y1 = 2 + D1, Y1Z2 = D1 + D2;
+};
+
+// LDS layout (in doubles) of a cell team of NW wavefronts (the last one also
+// evaluates the cell-local terms).
+template <int M, int NW>
+struct Lay {
+  using g = G<M>;
+  static constexpr int C = 0;                      // cell coefficients (cube)
+  static constexpr int F = C + g::CUBE;            // 8 face states (cubes), item q = f + 4 s
+  static constexpr int WSZ = 3 * g::CUBE + g::MISC;
+  static constexpr int W = F + 8 * g::CUBE;        // per-wavefront scratch, NW
+  static constexpr int T = W + NW * WSZ;           // 12 partial results (per-slot layout)
+  static constexpr int GR = T + 12 * g::SLOT;      // 4 face regularisation terms (per slot)
+  static constexpr int S = GR + 4 * g::SLOT;       // scalars
+  static constexpr int TOTAL = S + 64;
+  // partial results: 0..7 face-side items, 8 right-hand side (or the
+  // coarse-problem residual), 9 collision, 10/11 in-cell regularisation x/y
+  static constexpr int T_RHS = 8, T_Q = 9, T_GX = 10;
+  // scalar slots
+  static constexpr int SP = 0;    // face-state parameters, 8 x 4
+  static constexpr int SW = 32;   // weight of the regularisation jump per face, 4
+  static constexpr int SC = 36;   // cell u1, u2, th
+  static constexpr int SNU = 40;  // collision frequency of the cell
+  static constexpr int SAB = 41;  // team flag: abort
 };
 
 // Order LDS traffic of one wavefront: a wavefront-scope fence is a compiler
@@ -142,27 +176,24 @@ struct Slots {
   }
 };
 
+// Per-wavefront scratch and slot map.
 template <int M>
-struct Team {
+struct Wave {
   using g = G<M>;
-  double *bC, *bL, *bR, *bX, *bA, *bB, *misc;
+  double *bX, *bA, *bB, *misc;
   int lane;
   Slots<M> S;
   __device__ __forceinline__ void init(double *base, int ln) {
-    bC = base;
-    bL = base + g::CUBE;
-    bR = base + 2 * g::CUBE;
-    bX = base + 3 * g::CUBE;
-    bA = base + 4 * g::CUBE;
-    bB = base + 5 * g::CUBE;
-    misc = base + 6 * g::CUBE;
+    bX = base;
+    bA = base + g::CUBE;
+    bB = base + 2 * g::CUBE;
+    misc = base + 3 * g::CUBE;
     lane = ln;
     S.init(ln);
   }
 };
 
-// Cell data held by a team: basis parameters (uniform) and the lane's
-// coefficients.
+// Basis parameters (uniform) and the lane's coefficients of one record.
 template <int M>
 struct Cell {
   double u1, u2, th;
@@ -184,6 +215,18 @@ __device__ __forceinline__ void put(double *buf, const Slots<M> &S, const double
 #pragma unroll
   for (int r = 0; r < G<M>::SL; ++r)
     if (S.ok[r]) buf[S.ca[r]] = v[r];
+}
+
+template <int M>
+__device__ __forceinline__ void put_slots(double *buf, int lane, const double (&v)[G<M>::SL]) {
+#pragma unroll
+  for (int r = 0; r < G<M>::SL; ++r) buf[lane + WAVE * r] = v[r];
+}
+
+template <int M>
+__device__ __forceinline__ void get_slots(const double *buf, int lane, double (&v)[G<M>::SL]) {
+#pragma unroll
+  for (int r = 0; r < G<M>::SL; ++r) v[r] = buf[lane + WAVE * r];
 }
 
 // Coalesced write of a full record from (params, LDS cube); odd-alpha_3
@@ -221,12 +264,14 @@ __device__ __forceinline__ void tcoef(double du, double dth, double (&c)[M + 1])
   c[0] = 1.0;
   c[1] = -du;
 #pragma unroll
-  for (int k = 1; k < M; ++k) c[k + 1] = (-du * c[k] - dth * c[k - 1]) / (double)(k + 1);
+  for (int k = 1; k < M; ++k) c[k + 1] = (-du * c[k] - dth * c[k - 1]) * (1.0 / (k + 1));
 }
 
 // res = T(in) for the basis change by (du1, du2, dth): three 1-D lower-
 // triangular convolutions along alpha_1, alpha_2, alpha_3.  in, t1, t2 are
-// distinct LDS cubes; the result stays in registers.
+// distinct LDS cubes; the result stays in registers.  Terms beyond alpha_d
+// read a valid address with a zero coefficient, so every LDS read of a pass
+// is issued at once (adding fma(0, x, acc) leaves acc unchanged).
 template <int M>
 __device__ __forceinline__ void bchange(const double *in, double *t1, double *t2, double du1,
                                         double du2, double dth, const Slots<M> &S,
@@ -236,76 +281,76 @@ __device__ __forceinline__ void bchange(const double *in, double *t1, double *t2
   tcoef<M>(du1, dth, c);
 #pragma unroll
   for (int r = 0; r < g::SL; ++r) {
-    if (!S.ok[r]) continue;
     const double *p = in + S.ca[r];
-    double acc = p[0];
+    double x[M + 1];
 #pragma unroll
-    for (int k = 1; k <= M; ++k)
-      if (k <= S.a1[r]) acc = fma(c[k], p[-k], acc);
-    t1[S.ca[r]] = acc;
+    for (int k = 0; k <= M; ++k) x[k] = p[k <= S.a1[r] ? -k : 0];
+    double acc = x[0];
+#pragma unroll
+    for (int k = 1; k <= M; ++k) acc = fma(k <= S.a1[r] ? c[k] : 0.0, x[k], acc);
+    if (S.ok[r]) t1[S.ca[r]] = acc;
   }
   wsync();
   tcoef<M>(du2, dth, c);
 #pragma unroll
   for (int r = 0; r < g::SL; ++r) {
-    if (!S.ok[r]) continue;
     const double *p = t1 + S.ca[r];
-    double acc = p[0];
+    double x[M + 1];
 #pragma unroll
-    for (int k = 1; k <= M; ++k)
-      if (k <= S.a2[r]) acc = fma(c[k], p[-k * g::D1], acc);
-    t2[S.ca[r]] = acc;
+    for (int k = 0; k <= M; ++k) x[k] = p[k <= S.a2[r] ? -k * g::D1 : 0];
+    double acc = x[0];
+#pragma unroll
+    for (int k = 1; k <= M; ++k) acc = fma(k <= S.a2[r] ? c[k] : 0.0, x[k], acc);
+    if (S.ok[r]) t2[S.ca[r]] = acc;
   }
   wsync();
   tcoef<M>(0.0, dth, c);  // u_3 = 0 on both sides: only even powers survive
 #pragma unroll
   for (int r = 0; r < g::SL; ++r) {
     const double *p = t2 + S.ca[r];
-    double acc = S.ok[r] ? p[0] : 0.0;
+    double x[M / 2 + 1];
 #pragma unroll
-    for (int k = 1; 2 * k <= M; ++k)
-      if (S.ok[r] && k <= S.m[r]) acc = fma(c[2 * k], p[-k * g::D2], acc);
-    res[r] = acc;
+    for (int k = 0; 2 * k <= M; ++k) x[k] = p[k <= S.m[r] ? -k * g::D2 : 0];
+    double acc = x[0];
+#pragma unroll
+    for (int k = 1; 2 * k <= M; ++k) acc = fma(k <= S.m[r] ? c[2 * k] : 0.0, x[k], acc);
+    res[r] = S.ok[r] ? acc : 0.0;
   }
   wsync();
 }
 
 // (Pi_M xi_d f)_alpha = th f_{alpha-e_d} + u_d f_alpha + (alpha_d+1) f_{alpha+e_d}
-template <int M, int D>
-__device__ __forceinline__ double ximul(const double *f, double ud, double th, const Slots<M> &S,
-                                        int r) {
-  constexpr int st = D == 0 ? 1 : G<M>::D1;
+template <int M>
+__device__ __forceinline__ double ximul(int D, const double *f, double ud, double th,
+                                        const Slots<M> &S, int r) {
+  const int st = D == 0 ? 1 : G<M>::D1;
   const double *p = f + S.ca[r];
-  int ad = D == 0 ? S.a1[r] : S.a2[r];
-  double v = ud * p[0];
-  if (ad >= 1) v += th * p[-st];
-  if (S.n[r] < M) v += (ad + 1) * p[st];
+  const int ad = D == 0 ? S.a1[r] : S.a2[r];
+  const double x0 = p[0], xl = p[ad >= 1 ? -st : 0], xh = p[S.n[r] < M ? st : 0];
+  double v = ud * x0;
+  if (ad >= 1) v += th * xl;
+  if (S.n[r] < M) v += (ad + 1) * xh;
   return v;
 }
 
 // Regularisation term of direction D at |beta| = M (zero below):
 // (beta_D + 1) [sum_k f_{b+e_D-e_k} du_k + 1/2 sum_k f_{b+e_D-2e_k} dth],
-// du_3 = 0.  avgL/avgR: the term is taken of (fL + fR)/2 (both cubes, fR may
-// equal fL for the in-cell term).
-template <int M, int D>
-__device__ __forceinline__ double regul(const double *fL, const double *fR, double du1, double du2,
-                                        double dth, const Slots<M> &S, int r) {
+// du_3 = 0, taken of (fL + fR) / 2 (fR may equal fL for the in-cell term).
+template <int M>
+__device__ __forceinline__ double regul(int D, const double *fL, const double *fR, double du1,
+                                        double du2, double dth, const Slots<M> &S, int r) {
   using g = G<M>;
   if (!S.ok[r] || S.n[r] != M) return 0.0;
   const int base = S.ca[r] + (D == 0 ? 1 : g::D1);  // b + e_D
-  int b[3] = {S.a1[r], S.a2[r], 2 * S.m[r]};
-  b[D] += 1;
-  auto av = [&](int off) { return 0.5 * (fL[base + off] + fR[base + off]); };
+  const int b0 = S.a1[r] + (D == 0), b1 = S.a2[r] + (D == 1), b2 = 2 * S.m[r];
   double acc = 0.0;
-  // k = 1 (x)
-  if (b[0] >= 1) acc += av(-1) * du1;
-  if (b[0] >= 2) acc += 0.5 * av(-2) * dth;
-  // k = 2 (y)
-  if (b[1] >= 1) acc += av(-g::D1) * du2;
-  if (b[1] >= 2) acc += 0.5 * av(-2 * g::D1) * dth;
-  // k = 3 (z): du_3 = 0 and b - e_3 has odd alpha_3
-  if (b[2] >= 2) acc += 0.5 * av(-g::D2) * dth;
-  int bd = D == 0 ? S.a1[r] : S.a2[r];
+  if (b0 >= 1) acc += 0.5 * (fL[base - 1] + fR[base - 1]) * du1;
+  if (b0 >= 2) acc += 0.5 * (0.5 * (fL[base - 2] + fR[base - 2])) * dth;
+  if (b1 >= 1) acc += 0.5 * (fL[base - g::D1] + fR[base - g::D1]) * du2;
+  if (b1 >= 2) acc += 0.5 * (0.5 * (fL[base - 2 * g::D1] + fR[base - 2 * g::D1])) * dth;
+  // k = 3: du_3 = 0, and b - e_3 has odd alpha_3
+  if (b2 >= 2) acc += 0.5 * (0.5 * (fL[base - g::D2] + fR[base - g::D2])) * dth;
+  const int bd = D == 0 ? S.a1[r] : S.a2[r];
   return (bd + 1) * acc;
 }
 
@@ -339,7 +384,7 @@ __device__ __forceinline__ double halfI(const double *K, int k, int l) {
   double acc = 0.0;
   int jm = k < l ? k : l;
   for (int j = 0; j <= jm; ++j)
-    acc += c_fact.v[k] * c_fact.v[l] / (c_fact.v[j] * c_fact.v[k - j] * c_fact.v[l - j]) *
+    acc += c_fact.v[k] * c_fact.v[l] * (c_fact.inv[j] * c_fact.inv[k - j] * c_fact.inv[l - j]) *
            K[k + l - 2 * j];
   return acc;
 }
@@ -347,25 +392,25 @@ __device__ __forceinline__ double halfI(const double *K, int k, int l) {
 // Outward flux through a diffuse wall in the cell basis (reading of the
 // Maxwell boundary condition of Sec. 2.3 / Sec. 4): the leaving half-range
 // of the cell distribution plus the entering half of the wall Maxwellian,
-// whose density makes the net mass flux zero.  The cell's coefficients are
-// in the team's bC cube.
+// whose density makes the net mass flux zero.  fc: the cell's coefficients
+// (LDS cube).
 template <int M>
-__device__ void wall_flux(const LevelArgs &A, int wall, const Cell<M> &c, Team<M> &T,
-                          double (&phi)[G<M>::SL]) {
+__device__ void wall_flux(const LevelArgs &A, int wall, double u1, double u2, double th,
+                          const double *fc, Wave<M> &W, double (&phi)[G<M>::SL]) {
   using g = G<M>;
-  const Slots<M> &S = T.S;
-  const int lane = T.lane;
+  const Slots<M> &S = W.S;
+  const int lane = W.lane;
   const int d = (wall == 0 || wall == 2) ? 1 : 0;
   const double sig = (wall == 1 || wall == 2) ? 1.0 : -1.0;
-  const double sq = sqrt(c.th);
-  const double a = sig * (d == 0 ? c.u1 : c.u2) / sq;
-  double *K = T.misc + g::KOFF;
-  double *Jp = T.misc + g::JOFF;
-  double *bc = T.misc + g::BOFF;
+  const double sq = sqrt(th);
+  const double a = sig * (d == 0 ? u1 : u2) / sq;
+  double *K = W.misc + g::KOFF;
+  double *Jp = W.misc + g::JOFF;
+  double *bc = W.misc + g::BOFF;
   // K_n(a) = (2 pi)^-1/2 int_{-a}^inf He_n e^{-w^2/2}
   for (int n = lane; n <= 2 * M + 1; n += WAVE)
-    K[n] = n == 0 ? 0.5 * erfc(-a / sqrt(2.0))
-                  : hermite(n - 1, -a) * exp(-0.5 * a * a) / sqrt(2.0 * M_PI);
+    K[n] = n == 0 ? 0.5 * erfc(-a * M_SQRT1_2)
+                  : hermite(n - 1, -a) * exp(-0.5 * a * a) * (0.5 * M_2_SQRTPI * M_SQRT1_2);
   wsync();
   // J+_kl(a) = a I_kl + I_{k,l+1} + l I_{k,l-1}
   for (int t = lane; t < (M + 1) * (M + 1); t += WAVE) {
@@ -375,22 +420,23 @@ __device__ void wall_flux(const LevelArgs &A, int wall, const Cell<M> &c, Team<M
   wsync();
   // leaving half: sum_{beta_d} f_beta th^{(a_d-b_d)/2} sqrt(th) sig^{a_d+b_d} J+_{a_d b_d} / a_d!
   const double isq = 1.0 / sq;
+  const int dst = d == 0 ? 1 : g::D1;
 #pragma unroll
   for (int r = 0; r < g::SL; ++r) {
     double acc = 0.0;
     if (S.ok[r]) {
       int ad = d == 0 ? S.a1[r] : S.a2[r];
       int at = (d == 0 ? S.a2[r] : S.a1[r]) + 2 * S.m[r];  // transverse degree
-      int base = S.ca[r] - ad * (d == 0 ? 1 : g::D1);    // alpha with alpha_d = 0
+      int base = S.ca[r] - ad * dst;                      // alpha with alpha_d = 0
       double pa = 1.0;
       for (int q = 0; q < ad; ++q) pa *= sq;
+      const double ifa = c_fact.inv[ad];
       double ib = 1.0;
 #pragma unroll
       for (int bd = 0; bd <= M; ++bd) {
         if (bd + at <= M) {
           double sgn = ((ad + bd) & 1) ? sig : 1.0;
-          double fb = T.bC[base + bd * (d == 0 ? 1 : g::D1)];
-          acc += fb * (pa * ib) * sq * sgn * Jp[ad * (M + 1) + bd] / c_fact.v[ad];
+          acc += fc[base + bd * dst] * (pa * ib) * sq * sgn * Jp[ad * (M + 1) + bd] * ifa;
         }
         ib *= isq;
       }
@@ -405,101 +451,24 @@ __device__ void wall_flux(const LevelArgs &A, int wall, const Cell<M> &c, Team<M
   // entering half in the wall basis: only alpha = k e_d is non-zero
 #pragma unroll
   for (int r = 0; r < g::SL; ++r)
-    if (S.ok[r]) T.bX[S.ca[r]] = 0.0;
+    if (S.ok[r]) W.bX[S.ca[r]] = 0.0;
   wsync();
   if (lane <= M) {
     int k = lane;
     double pw = 1.0;
     for (int q = 0; q < k; ++q) pw *= sqw;
     double sgn = (k & 1) ? sig : 1.0;
-    T.bX[k * (d == 0 ? 1 : g::D1)] = rhow * pw * sqw * sgn * A.jminus[k];
+    W.bX[k * dst] = rhow * pw * sqw * sgn * A.jminus[k];
   }
   wsync();
-  double uw1 = d == 1 ? A.wall_u[wall] : 0.0, uw2 = d == 0 ? A.wall_u[wall] : 0.0;
+  const double uw1 = d == 1 ? A.wall_u[wall] : 0.0, uw2 = d == 0 ? A.wall_u[wall] : 0.0;
   double t[g::SL];
-  bchange<M>(T.bX, T.bA, T.bB, c.u1 - uw1, c.u2 - uw2, c.th - thw, S, t);
+  bchange<M>(W.bX, W.bA, W.bB, u1 - uw1, u2 - uw2, th - thw, S, t);
 #pragma unroll
   for (int r = 0; r < g::SL; ++r) phi[r] += t[r];
 }
 
-// Interior face with normal e_D between face states L and R (reading of the
-// numerical flux of Sec. 2.3: HLL with signal speeds u_D -/+ C_{M+1} sqrt(th),
-// the speeds of the CFL condition eq. (18)).  Both halves are projected into
-// the cell basis; the regularisation jump g is split w- (left cell) / w+
-// (right cell).  Adds (sgnF * F + w * g) / h to acc, w = w- if the cell is
-// the left one (cellIsLeft) else w+.
-template <int M, int D>
-__device__ void face(const LevelArgs &A, const Cell<M> &L, const Cell<M> &R, const Cell<M> &c,
-                     bool cellIsLeft, double h, Team<M> &T, double (&acc)[G<M>::SL]) {
-  using g = G<M>;
-  const Slots<M> &S = T.S;
-  put<M>(T.bL, S, L.f);
-  put<M>(T.bR, S, R.f);
-  wsync();
-  const double C = A.C;
-  const double uL = D == 0 ? L.u1 : L.u2, uR = D == 0 ? R.u1 : R.u2;
-  const double cL = C * sqrt(L.th), cR = C * sqrt(R.th);
-  const double lamL = fmin(uL - cL, uR - cR);
-  const double lamR = fmax(uL + cL, uR + cR);
-  int kase;
-  double wm, wp, den = lamR - lamL;
-  if (lamL >= 0.0) { kase = 0; wm = 0.0; wp = 1.0; }
-  else if (lamR <= 0.0) { kase = 1; wm = 1.0; wp = 0.0; }
-  else { kase = 2; wm = -lamL / den; wp = lamR / den; }
-  double F[g::SL];
-#pragma unroll
-  for (int r = 0; r < g::SL; ++r) F[r] = 0.0;
-  // left half A^L, in L's basis
-  if (kase != 1) {
-    double a[g::SL];
-#pragma unroll
-    for (int r = 0; r < g::SL; ++r) {
-      double Fx = S.ok[r] ? ximul<M, D>(T.bL, uL, L.th, S, r) : 0.0;
-      a[r] = kase == 0 ? Fx : (lamR * Fx - lamL * lamR * L.f[r]) / den;
-    }
-    if (L.u1 == c.u1 && L.u2 == c.u2 && L.th == c.th) {
-#pragma unroll
-      for (int r = 0; r < g::SL; ++r) F[r] += a[r];
-    } else {
-      put<M>(T.bX, S, a);
-      wsync();
-      double t[g::SL];
-      bchange<M>(T.bX, T.bA, T.bB, c.u1 - L.u1, c.u2 - L.u2, c.th - L.th, S, t);
-#pragma unroll
-      for (int r = 0; r < g::SL; ++r) F[r] += t[r];
-    }
-  }
-  if (kase != 0) {
-    double a[g::SL];
-#pragma unroll
-    for (int r = 0; r < g::SL; ++r) {
-      double Fx = S.ok[r] ? ximul<M, D>(T.bR, uR, R.th, S, r) : 0.0;
-      a[r] = kase == 1 ? Fx : (-lamL * Fx + lamL * lamR * R.f[r]) / den;
-    }
-    if (R.u1 == c.u1 && R.u2 == c.u2 && R.th == c.th) {
-#pragma unroll
-      for (int r = 0; r < g::SL; ++r) F[r] += a[r];
-    } else {
-      put<M>(T.bX, S, a);
-      wsync();
-      double t[g::SL];
-      bchange<M>(T.bX, T.bA, T.bB, c.u1 - R.u1, c.u2 - R.u2, c.th - R.th, S, t);
-#pragma unroll
-      for (int r = 0; r < g::SL; ++r) F[r] += t[r];
-    }
-  }
-  const double w = cellIsLeft ? wm : wp;
-  const double sgnF = cellIsLeft ? -1.0 : 1.0;
-  const double du1 = R.u1 - L.u1, du2 = R.u2 - L.u2, dth = R.th - L.th;
-#pragma unroll
-  for (int r = 0; r < g::SL; ++r) {
-    double gr = regul<M, D>(T.bL, T.bR, du1, du2, dth, S, r);
-    acc[r] += (sgnF * F[r] + w * gr) / h;
-  }
-  wsync();
-}
-
-// Face state of `c` on side `side` of direction D (eq. (15)): every variable
+// Face state of `c` on side `side` of a direction (eq. (15)): every variable
 // v -> v + side/2 * limited slope; zero slope when `flat`.
 template <int M>
 __device__ __forceinline__ void face_state(const Cell<M> &c, const Cell<M> &hi, const Cell<M> &lo,
@@ -512,75 +481,61 @@ __device__ __forceinline__ void face_state(const Cell<M> &c, const Cell<M> &hi, 
   out.u2 = c.u2 + 0.5 * side * limited(limiter, hi.u2, c.u2, lo.u2);
   out.th = c.th + 0.5 * side * limited(limiter, hi.th, c.th, lo.th);
 #pragma unroll
-  for (int r = 0; r < G<M>::SL; ++r) out.f[r] = c.f[r] + 0.5 * side * limited(limiter, hi.f[r], c.f[r], lo.f[r]);
+  for (int r = 0; r < G<M>::SL; ++r)
+    out.f[r] = c.f[r] + 0.5 * side * limited(limiter, hi.f[r], c.f[r], lo.f[r]);
 }
 
-// Contribution of direction D to R_ij: both faces (interior or wall) and, at
-// second order, the in-cell regularisation term.
-template <int M, int ORDER, int D>
-__device__ void direction(const LevelArgs &A, int k, int n, const Cell<M> &c, const Cell<M> &lo,
-                          const Cell<M> &hi, const Cell<M> &lolo, const Cell<M> &hihi, Team<M> &T,
-                          double (&acc)[G<M>::SL]) {
-  using g = G<M>;
-  const double h = D == 0 ? A.dx : A.dy;
-  const bool cflat = ORDER == 1 || k == 0 || k == n - 1;
-  double jump[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int si = 0; si < 2; ++si) {
-    const double side = si == 0 ? 1.0 : -1.0;
-    Cell<M> own;
-    face_state<M>(c, hi, lo, A.limiter, cflat, side, own);
-    if (si == 0) { jump[0] = own.u1; jump[1] = own.u2; jump[2] = own.th; }
-    else { jump[0] -= own.u1; jump[1] -= own.u2; jump[2] -= own.th; }
-    const int kn = k + (si == 0 ? 1 : -1);
-    if (kn < 0 || kn >= n) {
-      const int wall = D == 0 ? (si == 0 ? 1 : 3) : (si == 0 ? 2 : 0);
-      double phi[g::SL];
-      wall_flux<M>(A, wall, c, T, phi);
-#pragma unroll
-      for (int r = 0; r < g::SL; ++r) acc[r] -= phi[r] / h;
-      continue;
-    }
-    const bool nflat = ORDER == 1 || kn == 0 || kn == n - 1;
-    Cell<M> nb;
-    if (si == 0) face_state<M>(hi, hihi, c, A.limiter, nflat, -1.0, nb);
-    else face_state<M>(lo, c, lolo, A.limiter, nflat, 1.0, nb);
-    if (si == 0) face<M, D>(A, own, nb, c, true, h, T, acc);
-    else face<M, D>(A, nb, own, c, false, h, T, acc);
-  }
-  if (ORDER == 2) {
-#pragma unroll
-    for (int r = 0; r < g::SL; ++r)
-      acc[r] += regul<M, D>(T.bC, T.bC, jump[0], jump[1], jump[2], T.S, r) / h;
-  }
+// Local time step of eq. (18), capped so that nu dt <= nu_cap when nu_cap > 0.
+__device__ __forceinline__ double local_dt(const LevelArgs &A, double u1, double u2, double th,
+                                           double nu) {
+  const double sq = sqrt(th);
+  double dt = A.cfl / ((fabs(u1) + A.C * sq) * A.idx + (fabs(u2) + A.C * sq) * A.idy);
+  if (A.nu_cap > 0.0 && nu * dt > A.nu_cap) dt = A.nu_cap / nu;
+  return dt;
 }
 
-// Collision term Q = nu (f^E - f), eq. (5) and (29); BGK f^E = rho e_0
-// (eq. (6)); Shakhov adds (1-Pr) q_i / 5 at 3e_i and e_i + 2e_d (eq. (8)),
-// q_i from eq. (10).
+// Two-step update of Sec. 2.4: new (u, th) from the coefficients fs given in
+// the old basis (eq. (3)), re-expansion, and the exact constraints of
+// eq. (10).  Result left in cube W.bA and in out; false for rho <= 0,
+// th <= 0 or non-finite values.
 template <int M>
-__device__ __forceinline__ void collision(const LevelArgs &A, const Cell<M> &c, Team<M> &T,
-                                          double (&acc)[G<M>::SL]) {
+__device__ bool normalise(double ou1, double ou2, double oth, const double (&fs)[G<M>::SL],
+                          Wave<M> &W, Cell<M> &out) {
   using g = G<M>;
-  const double *f = T.bC;
-  const double rho = f[0];
-  const double nu = A.beta * sqrt(M_PI / 2.0) * rho * pow(c.th, 1.0 - A.omega) / A.Kn;
-  double c1 = 0.0, c2 = 0.0;
-  if (A.collision == 1) {
-    const double q1 = 2.0 * f[g::X3] + f[g::X3] + f[g::X1Y2] + f[g::X1Z2];
-    const double q2 = 2.0 * f[g::Y3] + f[g::X2Y1] + f[g::Y3] + f[g::Y1Z2];
-    c1 = (1.0 - A.Pr) * q1 / 5.0;
-    c2 = (1.0 - A.Pr) * q2 / 5.0;
-  }
+  put<M>(W.bX, W.S, fs);
+  wsync();
+  const double rho = W.bX[0];
+  const double fe1 = W.bX[g::E1], fe2 = W.bX[g::E2];
+  const double tr = W.bX[g::XX] + W.bX[g::YY] + W.bX[g::ZZ];
+  const double irho = 1.0 / rho;
+  const double u1n = ou1 + fe1 * irho, u2n = ou2 + fe2 * irho;
+  const double thn = oth + (2.0 * tr - (fe1 * fe1 + fe2 * fe2) * irho) * (irho * (1.0 / 3.0));
+  bool okp = rho > 0.0 && thn > 0.0 && isfinite(rho) && isfinite(thn) && isfinite(u1n) &&
+             isfinite(u2n);
+  if (!okp) return false;  // uniform branch
+  double t[g::SL];
+  bchange<M>(W.bX, W.bA, W.bB, u1n - ou1, u2n - ou2, thn - oth, W.S, t);
+  put<M>(W.bA, W.S, t);
+  wsync();
+  const double zz = -(W.bA[g::XX] + W.bA[g::YY]);
+  bool fin = true;
 #pragma unroll
   for (int r = 0; r < g::SL; ++r) {
-    if (!T.S.ok[r]) continue;
-    const int ca = T.S.ca[r];
-    double fE = ca == 0 ? rho : 0.0;
-    if (ca == g::X3 || ca == g::X1Y2 || ca == g::X1Z2) fE += c1;
-    if (ca == g::Y3 || ca == g::X2Y1 || ca == g::Y1Z2) fE += c2;
-    acc[r] += nu * (fE - c.f[r]);
+    const int ca = W.S.ca[r];
+    if (ca == g::E1 || ca == g::E2) t[r] = 0.0;
+    if (ca == g::ZZ) t[r] = zz;
+    if (W.S.ok[r] && !isfinite(t[r])) fin = false;
   }
+  wsync();
+  if (W.lane < 2) W.bA[W.lane == 0 ? g::E1 : g::E2] = 0.0;
+  if (W.lane == 0) W.bA[g::ZZ] = zz;
+  wsync();
+  out.u1 = u1n;
+  out.u2 = u2n;
+  out.th = thn;
+#pragma unroll
+  for (int r = 0; r < g::SL; ++r) out.f[r] = t[r];
+  return __ballot(!fin) == 0;
 }
 
 template <int M>
@@ -588,107 +543,307 @@ __device__ __forceinline__ const double *recp(const LevelArgs &A, const double *
   return st + ((size_t)j * A.nx + i) * G<M>::STRIDE;
 }
 
-// R_ij(f) of eq. (13) for cell (i, j): team-wide, result in acc; c receives
-// the cell (its coefficients are also left in bC).
-template <int M, int ORDER>
-__device__ void cell_R(const LevelArgs &A, const double *__restrict__ st, int i, int j, Team<M> &T,
-                       Cell<M> &c, double (&acc)[G<M>::SL]) {
+// ---------------------------------------------------------------------------
+// The cell team: R_ij(f) of eq. (13) and what is done with it
+// ---------------------------------------------------------------------------
+
+enum { MODE_SWEEP = 0, MODE_DEFECT = 1, MODE_FAS = 2 };
+
+// Faces: 0 = E (+x), 1 = W (-x), 2 = N (+y), 3 = S (-y).  Item q = f + 4 s:
+// s = 0 the cell's own face state, s = 1 the neighbour's.
+__device__ __forceinline__ int face_dir(int f) { return f >> 1; }
+__device__ __forceinline__ double face_side(int f) { return (f & 1) ? -1.0 : 1.0; }
+__device__ __forceinline__ int face_wall(int f) { return f == 0 ? 1 : f == 1 ? 3 : f == 2 ? 2 : 0; }
+
+// Evaluate cell (i, j) with a team of NW wavefronts and
+//  MODE_SWEEP : update the cell in place (Alg. 1): f <- normalise(f + dt (R - r)),
+//  MODE_DEFECT: out = r - R(f) in the cell basis, norm_part[cell] = weighted norm^2 * ds,
+//  MODE_FAS   : out = R(f) + Radd (coarse right-hand side of eq. (22)).
+// Every wavefront returns; the team's LDS may be reused after a barrier.
+// A non-physical update sets bit 0 of *err and leaves the cell unchanged.
+template <int M, int ORDER, int NW, int MODE>
+__device__ void cell_team(const LevelArgs &A, double *lds, double *__restrict__ st,
+                          const double *__restrict__ rhs, const double *__restrict__ Radd,
+                          double *__restrict__ out, double *__restrict__ norm_part, int i, int j,
+                          int *err) {
   using g = G<M>;
-  Cell<M> W, E, Sx, Nx, WW, EE, SS, NN;
-  load_cell<M>(recp<M>(A, st, i, j), T.S, c);
-  const bool hasW = i > 0, hasE = i < A.nx - 1, hasS = j > 0, hasN = j < A.ny - 1;
-  if (hasW) load_cell<M>(recp<M>(A, st, i - 1, j), T.S, W); else W = c;
-  if (hasE) load_cell<M>(recp<M>(A, st, i + 1, j), T.S, E); else E = c;
-  if (hasS) load_cell<M>(recp<M>(A, st, i, j - 1), T.S, Sx); else Sx = c;
-  if (hasN) load_cell<M>(recp<M>(A, st, i, j + 1), T.S, Nx); else Nx = c;
-  if (ORDER == 2) {
-    if (i > 1) load_cell<M>(recp<M>(A, st, i - 2, j), T.S, WW); else WW = W;
-    if (i < A.nx - 2) load_cell<M>(recp<M>(A, st, i + 2, j), T.S, EE); else EE = E;
-    if (j > 1) load_cell<M>(recp<M>(A, st, i, j - 2), T.S, SS); else SS = Sx;
-    if (j < A.ny - 2) load_cell<M>(recp<M>(A, st, i, j + 2), T.S, NN); else NN = Nx;
-  } else {
-    WW = W; EE = E; SS = Sx; NN = Nx;
+  using L = Lay<M, NW>;
+  const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  Wave<M> W;
+  W.init(lds + L::W + wv * L::WSZ, lane);
+  const Slots<M> &S = W.S;
+  double *bC = lds + L::C;
+  double *sc = lds + L::S;
+  const int nx = A.nx, ny = A.ny;
+  const int cellidx = j * nx + i;
+
+  // ---- phase 0: face states of this wavefront's items -------------------
+  Cell<M> c;
+  load_cell<M>(recp<M>(A, st, i, j), S, c);
+  if (wv == NW - 1) {
+    put<M>(bC, S, c.f);
+    // collision frequency of eq. (29); rho = f_0 sits in lane 0, slot 0
+    const double rho = __shfl(c.f[0], 0);
+    const double nu = A.beta * sqrt(M_PI / 2.0) * rho * pow(c.th, 1.0 - A.omega) / A.Kn;
+    if (lane == 0) {
+      sc[L::SC] = c.u1;
+      sc[L::SC + 1] = c.u2;
+      sc[L::SC + 2] = c.th;
+      sc[L::SNU] = nu;
+    }
   }
-  put<M>(T.bC, T.S, c.f);
+  for (int q = wv; q < 8; q += NW) {
+    const int f = q & 3, s = q >> 2, D = face_dir(f);
+    const double side = face_side(f);
+    const int k = D == 0 ? i : j, n = D == 0 ? nx : ny;
+    const int sd = (int)side;
+    const bool wall = (k + sd < 0) || (k + sd >= n);
+    Cell<M> X;
+    if (s == 0) {
+      const bool flat = ORDER == 1 || k == 0 || k == n - 1;
+      if (flat) X = c;
+      else {
+        Cell<M> hi, lo;
+        load_cell<M>(D == 0 ? recp<M>(A, st, i + 1, j) : recp<M>(A, st, i, j + 1), S, hi);
+        load_cell<M>(D == 0 ? recp<M>(A, st, i - 1, j) : recp<M>(A, st, i, j - 1), S, lo);
+        face_state<M>(c, hi, lo, A.limiter, false, side, X);
+      }
+    } else {
+      if (wall) continue;
+      const int kn = k + sd;
+      const bool nflat = ORDER == 1 || kn == 0 || kn == n - 1;
+      Cell<M> nb;
+      load_cell<M>(D == 0 ? recp<M>(A, st, i + sd, j) : recp<M>(A, st, i, j + sd), S, nb);
+      if (nflat) X = nb;
+      else {
+        Cell<M> far;
+        load_cell<M>(D == 0 ? recp<M>(A, st, i + 2 * sd, j) : recp<M>(A, st, i, j + 2 * sd), S, far);
+        // neighbour's face on the cell's side: slope from (far, nb, c)
+        if (sd > 0) face_state<M>(nb, far, c, A.limiter, false, -side, X);
+        else face_state<M>(nb, c, far, A.limiter, false, -side, X);
+      }
+    }
+    put<M>(lds + L::F + q * g::CUBE, S, X.f);
+    if (lane == 0) {
+      sc[L::SP + 4 * q] = X.u1;
+      sc[L::SP + 4 * q + 1] = X.u2;
+      sc[L::SP + 4 * q + 2] = X.th;
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 1: half-fluxes projected into the cell basis ---------------
+  for (int q = wv; q < 8; q += NW) {
+    const int f = q & 3, s = q >> 2, D = face_dir(f);
+    const double side = face_side(f);
+    const int k = D == 0 ? i : j, n = D == 0 ? nx : ny;
+    const int sd = (int)side;
+    const bool wall = (k + sd < 0) || (k + sd >= n);
+    double T[g::SL];
+    if (wall) {
+      if (s == 1) continue;
+      wall_flux<M>(A, face_wall(f), c.u1, c.u2, c.th, bC, W, T);
+      put_slots<M>(lds + L::T + q * g::SLOT, lane, T);
+      continue;
+    }
+    // L / R face states: the cell is left of its E and N faces
+    const int qo = f, qn = f + 4;
+    const int qL = sd > 0 ? qo : qn, qR = sd > 0 ? qn : qo;
+    const double uL = sc[L::SP + 4 * qL + D], thL = sc[L::SP + 4 * qL + 2];
+    const double uR = sc[L::SP + 4 * qR + D], thR = sc[L::SP + 4 * qR + 2];
+    const double cL = A.C * sqrt(thL), cR = A.C * sqrt(thR);
+    const double lamL = fmin(uL - cL, uR - cR);
+    const double lamR = fmax(uL + cL, uR + cR);
+    int kase;
+    double wm, wp;
+    const double iden = 1.0 / (lamR - lamL);
+    if (lamL >= 0.0) { kase = 0; wm = 0.0; wp = 1.0; }
+    else if (lamR <= 0.0) { kase = 1; wm = 1.0; wp = 0.0; }
+    else { kase = 2; wm = -lamL * iden; wp = lamR * iden; }
+    const bool isL = q == qL;
+    const double *fx = lds + L::F + q * g::CUBE;
+    const double ux = sc[L::SP + 4 * q + D], thx = sc[L::SP + 4 * q + 2];
+    if ((isL && kase == 1) || (!isL && kase == 0)) {
 #pragma unroll
-  for (int r = 0; r < g::SL; ++r) acc[r] = 0.0;
-  wsync();
-  direction<M, ORDER, 0>(A, i, A.nx, c, W, E, WW, EE, T, acc);
-  direction<M, ORDER, 1>(A, j, A.ny, c, Sx, Nx, SS, NN, T, acc);
-  collision<M>(A, c, T, acc);
-}
-
-// Local time step of eq. (18), capped so that nu dt <= nu_cap when nu_cap > 0.
-__device__ __forceinline__ double local_dt(const LevelArgs &A, double u1, double u2, double th,
-                                           double rho) {
-  const double sq = sqrt(th);
-  double dt = A.cfl / ((fabs(u1) + A.C * sq) / A.dx + (fabs(u2) + A.C * sq) / A.dy);
-  if (A.nu_cap > 0.0) {
-    const double nu = A.beta * sqrt(M_PI / 2.0) * rho * pow(th, 1.0 - A.omega) / A.Kn;
-    if (nu * dt > A.nu_cap) dt = A.nu_cap / nu;
+      for (int r = 0; r < g::SL; ++r) T[r] = 0.0;
+    } else {
+      double a[g::SL];
+#pragma unroll
+      for (int r = 0; r < g::SL; ++r) {
+        const double Fx = S.ok[r] ? ximul<M>(D, fx, ux, thx, S, r) : 0.0;
+        const double fr = S.ok[r] ? fx[S.ca[r]] : 0.0;
+        if (kase != 2) a[r] = Fx;
+        else if (isL) a[r] = (lamR * Fx - lamL * lamR * fr) * iden;
+        else a[r] = (-lamL * Fx + lamL * lamR * fr) * iden;
+      }
+      const double xu1 = sc[L::SP + 4 * q], xu2 = sc[L::SP + 4 * q + 1];
+      if (xu1 == c.u1 && xu2 == c.u2 && thx == c.th) {
+#pragma unroll
+        for (int r = 0; r < g::SL; ++r) T[r] = a[r];
+      } else {
+        put<M>(W.bX, S, a);
+        wsync();
+        bchange<M>(W.bX, W.bA, W.bB, c.u1 - xu1, c.u2 - xu2, c.th - thx, S, T);
+      }
+    }
+    put_slots<M>(lds + L::T + q * g::SLOT, lane, T);
+    if (s == 0) {
+      // regularisation jump of the face, straight path from L to R
+      const double *fL = lds + L::F + qL * g::CUBE, *fR = lds + L::F + qR * g::CUBE;
+      const double du1 = sc[L::SP + 4 * qR] - sc[L::SP + 4 * qL];
+      const double du2 = sc[L::SP + 4 * qR + 1] - sc[L::SP + 4 * qL + 1];
+      const double dth = thR - thL;
+      double gr[g::SL];
+#pragma unroll
+      for (int r = 0; r < g::SL; ++r) gr[r] = regul<M>(D, fL, fR, du1, du2, dth, S, r);
+      put_slots<M>(lds + L::GR + f * g::SLOT, lane, gr);
+      if (lane == 0) sc[L::SW + f] = sd > 0 ? wm : wp;
+    }
   }
-  return dt;
+  if (wv == NW - 1) {
+    // cell-local terms on the last wavefront
+    const double rho = bC[0];
+    const double nu = sc[L::SNU];
+    double T[g::SL];
+    // collision Q = nu (f^E - f), eq. (5), (29); Shakhov f^E from eq. (8)
+    double c1 = 0.0, c2 = 0.0;
+    if (A.collision == 1) {
+      const double q1 = 2.0 * bC[g::X3] + bC[g::X3] + bC[g::X1Y2] + bC[g::X1Z2];
+      const double q2 = 2.0 * bC[g::Y3] + bC[g::X2Y1] + bC[g::Y3] + bC[g::Y1Z2];
+      c1 = (1.0 - A.Pr) * q1 * 0.2;
+      c2 = (1.0 - A.Pr) * q2 * 0.2;
+    }
+#pragma unroll
+    for (int r = 0; r < g::SL; ++r) {
+      const int ca = S.ca[r];
+      double fE = ca == 0 ? rho : 0.0;
+      if (ca == g::X3 || ca == g::X1Y2 || ca == g::X1Z2) fE += c1;
+      if (ca == g::Y3 || ca == g::X2Y1 || ca == g::Y1Z2) fE += c2;
+      T[r] = S.ok[r] ? nu * (fE - c.f[r]) : 0.0;
+    }
+    put_slots<M>(lds + L::T + L::T_Q * g::SLOT, lane, T);
+    if (ORDER == 2) {
+      // in-cell regularisation: jump between the cell's own two face states
+#pragma unroll
+      for (int D = 0; D < 2; ++D) {
+        const int fp = 2 * D, fm = 2 * D + 1;
+        const double j1 = sc[L::SP + 4 * fp] - sc[L::SP + 4 * fm];
+        const double j2 = sc[L::SP + 4 * fp + 1] - sc[L::SP + 4 * fm + 1];
+        const double j3 = sc[L::SP + 4 * fp + 2] - sc[L::SP + 4 * fm + 2];
+#pragma unroll
+        for (int r = 0; r < g::SL; ++r) T[r] = regul<M>(D, bC, bC, j1, j2, j3, S, r);
+        put_slots<M>(lds + L::T + (L::T_GX + D) * g::SLOT, lane, T);
+      }
+    }
+    const double *rr = MODE == MODE_FAS ? Radd : rhs;
+    if (rr) {
+      // right-hand side (Alg. 1) or the restricted residual (eq. (22)) in
+      // the cell basis
+      Cell<M> r;
+      load_cell<M>(recp<M>(A, rr, i, j), S, r);
+      if ((r.u1 == c.u1 && r.u2 == c.u2 && r.th == c.th) || MODE == MODE_FAS) {
+#pragma unroll
+        for (int q = 0; q < g::SL; ++q) T[q] = r.f[q];
+      } else {
+        put<M>(W.bX, S, r.f);
+        wsync();
+        bchange<M>(W.bX, W.bA, W.bB, c.u1 - r.u1, c.u2 - r.u2, c.th - r.th, S, T);
+      }
+      put_slots<M>(lds + L::T + L::T_RHS * g::SLOT, lane, T);
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 2 (wavefront 0): assemble R_ij in a fixed order ------------
+  if (wv == 0) {
+    double R[g::SL];
+#pragma unroll
+    for (int r = 0; r < g::SL; ++r) R[r] = 0.0;
+#pragma unroll
+    for (int D = 0; D < 2; ++D) {
+      const int k = D == 0 ? i : j, n = D == 0 ? nx : ny;
+      const double ih = D == 0 ? A.idx : A.idy;
+#pragma unroll
+      for (int sdi = 0; sdi < 2; ++sdi) {
+        const int f = 2 * D + sdi;
+        const int sd = sdi == 0 ? 1 : -1;
+        double TL[g::SL], TR[g::SL];
+        if (k + sd < 0 || k + sd >= n) {
+          get_slots<M>(lds + L::T + f * g::SLOT, lane, TL);
+#pragma unroll
+          for (int r = 0; r < g::SL; ++r) R[r] -= TL[r] * ih;
+          continue;
+        }
+        const int qL = sd > 0 ? f : f + 4, qR = sd > 0 ? f + 4 : f;
+        double gr[g::SL];
+        get_slots<M>(lds + L::T + qL * g::SLOT, lane, TL);
+        get_slots<M>(lds + L::T + qR * g::SLOT, lane, TR);
+        get_slots<M>(lds + L::GR + f * g::SLOT, lane, gr);
+        const double w = sc[L::SW + f];
+        const double sgnF = sd > 0 ? -1.0 : 1.0;
+#pragma unroll
+        for (int r = 0; r < g::SL; ++r) R[r] += (sgnF * (TL[r] + TR[r]) + w * gr[r]) * ih;
+      }
+      if (ORDER == 2) {
+        double gc[g::SL];
+        get_slots<M>(lds + L::T + (L::T_GX + D) * g::SLOT, lane, gc);
+#pragma unroll
+        for (int r = 0; r < g::SL; ++r) R[r] += gc[r] * ih;
+      }
+    }
+    {
+      double q[g::SL];
+      get_slots<M>(lds + L::T + L::T_Q * g::SLOT, lane, q);
+#pragma unroll
+      for (int r = 0; r < g::SL; ++r) R[r] += q[r];
+    }
+    const double *rr = MODE == MODE_FAS ? Radd : rhs;
+    double rv[g::SL];
+    if (rr) get_slots<M>(lds + L::T + L::T_RHS * g::SLOT, lane, rv);
+    if (MODE == MODE_SWEEP) {
+      const double dt = local_dt(A, c.u1, c.u2, c.th, sc[L::SNU]);
+      double fs[g::SL];
+#pragma unroll
+      for (int r = 0; r < g::SL; ++r) fs[r] = c.f[r] + dt * (rr ? R[r] - rv[r] : R[r]);
+      Cell<M> nc;
+      if (normalise<M>(c.u1, c.u2, c.th, fs, W, nc))
+        store_record<M>(const_cast<double *>(recp<M>(A, st, i, j)), nc.u1, nc.u2, nc.th, W.bA, lane);
+      else if (lane == 0)
+        atomicOr(err, 1);
+    } else {
+      double o[g::SL];
+#pragma unroll
+      for (int r = 0; r < g::SL; ++r)
+        o[r] = MODE == MODE_FAS ? R[r] + rv[r] : (rr ? rv[r] : 0.0) - R[r];
+      if (out) {
+        put<M>(W.bA, S, o);
+        wsync();
+        store_record<M>(out + (size_t)cellidx * g::STRIDE, c.u1, c.u2, c.th, W.bA, lane);
+      }
+      if (MODE == MODE_DEFECT && norm_part) {
+        double s2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < g::SL; ++q) {
+          if (!S.ok[q]) continue;
+          const double w = c_fact.v[S.a1[q]] * c_fact.v[S.a2[q]] * c_fact.v[2 * S.m[q]];
+          s2 += w * pow(c.th, -(double)S.n[q]) * o[q] * o[q];
+        }
+#pragma unroll
+        for (int off = WAVE / 2; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
+        if (lane == 0) norm_part[cellidx] = s2 * A.ds;
+      }
+    }
+  }
 }
 
-// Load a right-hand-side record and project it into the basis (u1, u2, th).
+// Team width: 8 wavefronts (one face-side item each) while the LDS of a team
+// fits comfortably, 4 at M >= 6 (two items each).  At most 8 wavefronts keeps
+// the budget at 256 VGPRs per lane.
 template <int M>
-__device__ __forceinline__ void rhs_in_basis(const double *__restrict__ rrec, double u1, double u2,
-                                             double th, Team<M> &T, double (&out)[G<M>::SL]) {
-  Cell<M> r;
-  load_cell<M>(rrec, T.S, r);
-  if (r.u1 == u1 && r.u2 == u2 && r.th == th) {
-#pragma unroll
-    for (int q = 0; q < G<M>::SL; ++q) out[q] = r.f[q];
-    return;
-  }
-  put<M>(T.bX, T.S, r.f);
-  wsync();
-  bchange<M>(T.bX, T.bA, T.bB, u1 - r.u1, u2 - r.u2, th - r.th, T.S, out);
-}
-
-// Two-step update of Sec. 2.4: new (u, th) from the coefficients f* given in
-// the old basis (eq. (3)), re-expansion, and the exact constraints of
-// eq. (10).  Result in cube bA and in out; returns false for rho <= 0,
-// th <= 0 or non-finite values.
-template <int M>
-__device__ bool normalise(const Cell<M> &old, const double (&fs)[G<M>::SL], Team<M> &T,
-                          Cell<M> &out) {
-  using g = G<M>;
-  put<M>(T.bX, T.S, fs);
-  wsync();
-  const double rho = T.bX[0];
-  const double fe1 = T.bX[g::E1], fe2 = T.bX[g::E2];
-  const double tr = T.bX[g::XX] + T.bX[g::YY] + T.bX[g::ZZ];
-  const double u1n = old.u1 + fe1 / rho, u2n = old.u2 + fe2 / rho;
-  const double thn = old.th + (2.0 * tr - (fe1 * fe1 + fe2 * fe2) / rho) / (3.0 * rho);
-  bool okp = rho > 0.0 && thn > 0.0 && isfinite(rho) && isfinite(thn) && isfinite(u1n) &&
-             isfinite(u2n);
-  if (!okp) return false;  // uniform branch
-  double t[g::SL];
-  bchange<M>(T.bX, T.bA, T.bB, u1n - old.u1, u2n - old.u2, thn - old.th, T.S, t);
-  put<M>(T.bA, T.S, t);
-  wsync();
-  const double zz = -(T.bA[g::XX] + T.bA[g::YY]);
-  bool fin = true;
-#pragma unroll
-  for (int r = 0; r < g::SL; ++r) {
-    const int ca = T.S.ca[r];
-    if (ca == g::E1 || ca == g::E2) t[r] = 0.0;
-    if (ca == g::ZZ) t[r] = zz;
-    if (T.S.ok[r] && !isfinite(t[r])) fin = false;
-  }
-  wsync();
-  if (T.lane < 2) T.bA[T.lane == 0 ? g::E1 : g::E2] = 0.0;
-  if (T.lane == 0) T.bA[g::ZZ] = zz;
-  wsync();
-  out.u1 = u1n;
-  out.u2 = u2n;
-  out.th = thn;
-#pragma unroll
-  for (int r = 0; r < g::SL; ++r) out.f[r] = t[r];
-  // all lanes agree (ballot over the finiteness of every coefficient)
-  return __ballot(!fin) == 0;
-}
+struct TeamWidth {
+  static constexpr int NW = M <= 5 ? 8 : 4;
+  static constexpr int THREADS = NW * WAVE;
+};
 
 // ---------------------------------------------------------------------------
 // Kernels
@@ -699,85 +854,103 @@ __device__ bool normalise(const Cell<M> &old, const double (&fs)[G<M>::SL], Team
 // coordinates.  Cells of one diagonal never read each other (cross-shaped
 // stencil of radius <= 2), earlier diagonals are already updated and later
 // ones are not: the serial Gauss-Seidel order of Alg. 1 exactly.
-template <int M, int ORDER>
-__global__ __launch_bounds__(WAVE) void k_sweep_diag(LevelArgs A, double *__restrict__ st,
-                                                     const double *__restrict__ rhs, int dir, int t,
-                                                     int a0, int *err) {
-  using g = G<M>;
-  __shared__ double lds[g::TEAM_LDS];
-  Team<M> T;
-  T.init(lds, threadIdx.x);
+template <int M, int ORDER, int NW>
+__global__ __launch_bounds__(NW * WAVE) void k_sweep_diag(LevelArgs A, double *__restrict__ st,
+                                                                const double *__restrict__ rhs,
+                                                                int dir, int t, int a0, int *err) {
+  __shared__ double lds[Lay<M, NW>::TOTAL];
   const int a = a0 + blockIdx.x, b = t - a;
   const bool irev = dir == 1 || dir == 2, jrev = dir == 2 || dir == 3;
   const int i = irev ? A.nx - 1 - a : a, j = jrev ? A.ny - 1 - b : b;
-  Cell<M> c;
-  double R[g::SL];
-  cell_R<M, ORDER>(A, st, i, j, T, c, R);
-  const double dt = local_dt(A, c.u1, c.u2, c.th, T.bC[0]);
-  if (rhs) {
-    double r[g::SL];
-    rhs_in_basis<M>(recp<M>(A, rhs, i, j), c.u1, c.u2, c.th, T, r);
-#pragma unroll
-    for (int q = 0; q < g::SL; ++q) R[q] -= r[q];
-  }
-  double fs[g::SL];
-#pragma unroll
-  for (int q = 0; q < g::SL; ++q) fs[q] = c.f[q] + dt * R[q];
-  Cell<M> nc;
-  if (normalise<M>(c, fs, T, nc)) {
-    store_record<M>(const_cast<double *>(recp<M>(A, st, i, j)), nc.u1, nc.u2, nc.th, T.bA, T.lane);
-  } else if (T.lane == 0) {
-    atomicOr(err, 1);
+  cell_team<M, ORDER, NW, MODE_SWEEP>(A, lds, st, rhs, nullptr, nullptr, nullptr, i, j, err);
+}
+
+// Wait until *flag >= target (agent-scope acquire).  Bounded: gives up after
+// `limit` ticks of the 100 MHz wall clock or when another team has aborted;
+// returns false then.
+__device__ __forceinline__ bool wait_at_least(const int *flag, int target, int *abort_flag,
+                                              unsigned long long limit) {
+  const unsigned long long t0 = wall_clock64();
+  for (;;) {
+    if (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target) return true;
+    if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    if (wall_clock64() - t0 > limit) {
+      __hip_atomic_fetch_or(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
   }
 }
 
-// Residual over all cells.  mode 0: out = r - R(f) in the cell basis (rhs
-// may be NULL), norm_part[cell] = ds * sum_alpha alpha! th^-|alpha| out^2.
-// mode 1: out = R(f) + Radd (coarse right-hand side of eq. (22); Radd is in
-// the basis of f).
-template <int M, int ORDER>
-__global__ __launch_bounds__(WAVE) void k_residual(LevelArgs A, const double *__restrict__ st,
-                                                   const double *__restrict__ rhs,
-                                                   const double *__restrict__ Radd,
-                                                   double *__restrict__ out,
-                                                   double *__restrict__ norm_part, int mode) {
-  using g = G<M>;
-  __shared__ double lds[g::TEAM_LDS];
-  Team<M> T;
-  T.init(lds, threadIdx.x);
-  const int cell = blockIdx.x;
-  const int i = cell % A.nx, j = cell / A.nx;
-  Cell<M> c;
-  double R[g::SL], o[g::SL];
-  cell_R<M, ORDER>(A, st, i, j, T, c, R);
-  if (mode == 1) {
-    Cell<M> ra;
-    load_cell<M>(recp<M>(A, Radd, i, j), T.S, ra);
-#pragma unroll
-    for (int q = 0; q < g::SL; ++q) o[q] = R[q] + ra.f[q];
-  } else {
-    double r[g::SL];
-    if (rhs) rhs_in_basis<M>(recp<M>(A, rhs, i, j), c.u1, c.u2, c.th, T, r);
-#pragma unroll
-    for (int q = 0; q < g::SL; ++q) o[q] = (rhs ? r[q] : 0.0) - R[q];
-  }
-  if (out) {
-    put<M>(T.bA, T.S, o);
-    wsync();
-    store_record<M>(out + (size_t)cell * g::STRIDE, c.u1, c.u2, c.th, T.bA, T.lane);
-  }
-  if (norm_part && mode == 0) {
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < g::SL; ++q) {
-      if (!T.S.ok[q]) continue;
-      const double w = c_fact.v[T.S.a1[q]] * c_fact.v[T.S.a2[q]] * c_fact.v[2 * T.S.m[q]];
-      s += w * pow(c.th, -(double)T.S.n[q]) * o[q] * o[q];
+// Persistent fast sweeping: `nsweep` directional sweeps (directions taken
+// from dirs[], 2 bits each) in one launch.  Workgroup g owns grid column
+// i = g and updates its cells in the order of each sweep.  Cell (i, j) of
+// sweep s may start when (a) the previous column in this sweep's order has
+// finished row j (so the cells before it in the serial order are final) and
+// (b) the columns i-2 .. i+2 have finished row j of sweep s-1 (so nothing
+// still reads the cell's old value and its stencil holds final values).
+// Progress counters only grow: column i has finished base + s * ny + b + 1
+// cells after row b of sweep s.  Every wait is bounded (abort flag + wall
+// clock), so the grid always drains.
+template <int M, int ORDER, int NW>
+__global__ __launch_bounds__(NW * WAVE) void k_sweep_persist(
+    LevelArgs A, double *__restrict__ st, const double *__restrict__ rhs, int nsweep,
+    unsigned dirs, int *cnt, int base, int *err, int *abort_flag, unsigned long long limit) {
+  using L = Lay<M, NW>;
+  __shared__ double lds[L::TOTAL];
+  double *sc = lds + L::S;
+  const int i = blockIdx.x;
+  const int nx = A.nx, ny = A.ny;
+  for (int s = 0; s < nsweep; ++s) {
+    const int dir = (dirs >> (2 * s)) & 3;
+    const bool irev = dir == 1 || dir == 2, jrev = dir == 2 || dir == 3;
+    const int prev = irev ? i + 1 : i - 1;
+    const bool hasPrev = irev ? i < nx - 1 : i > 0;
+    const int pdir = s > 0 ? (dirs >> (2 * (s - 1))) & 3 : 0;
+    const bool pjrev = pdir == 2 || pdir == 3;
+    const int sbase = base + s * ny;
+    for (int b = 0; b < ny; ++b) {
+      const int j = jrev ? ny - 1 - b : b;
+      if (threadIdx.x == 0) {
+        bool ok = true;
+        if (hasPrev) ok = wait_at_least(cnt + prev, sbase + b + 1, abort_flag, limit);
+        if (ok && s > 0) {
+          const int bp = pjrev ? ny - 1 - j : j;  // row j in the previous sweep's order
+          for (int d = -2; d <= 2 && ok; ++d) {
+            const int ii = i + d;
+            if (d == 0 || ii < 0 || ii >= nx) continue;
+            ok = wait_at_least(cnt + ii, sbase - ny + bp + 1, abort_flag, limit);
+          }
+        }
+        sc[L::SAB] = ok ? 0.0 : 1.0;
+      }
+      __syncthreads();
+      if (sc[L::SAB] != 0.0) {
+        if (threadIdx.x == 0) atomicOr(err, 4);
+        return;  // uniform across the team
+      }
+      cell_team<M, ORDER, NW, MODE_SWEEP>(A, lds, st, rhs, nullptr, nullptr, nullptr, i, j, err);
+      if (threadIdx.x == 0) {
+        // wavefront 0 stored the cell; publish it (agent-scope release)
+        __hip_atomic_store(cnt + i, sbase + b + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      __syncthreads();
     }
-#pragma unroll
-    for (int off = WAVE / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (T.lane == 0) norm_part[cell] = s * A.ds;
   }
+}
+
+// Residual over all cells (MODE_DEFECT) or the coarse right-hand side
+// (MODE_FAS), one team per cell.
+template <int M, int ORDER, int NW, int MODE>
+__global__ __launch_bounds__(NW * WAVE) void k_residual(LevelArgs A, const double *__restrict__ st,
+                                                              const double *__restrict__ rhs,
+                                                              const double *__restrict__ Radd,
+                                                              double *__restrict__ out,
+                                                              double *__restrict__ norm_part) {
+  __shared__ double lds[Lay<M, NW>::TOTAL];
+  const int cell = blockIdx.x;
+  cell_team<M, ORDER, NW, MODE>(A, lds, const_cast<double *>(st), rhs, Radd, out, norm_part,
+                                cell % A.nx, cell / A.nx, nullptr);
 }
 
 // Restriction (Sec. 3.2.2, eq. (24)-(25)): coarse cell (I, J) from fine cells
@@ -788,14 +961,15 @@ __global__ __launch_bounds__(WAVE) void k_restrict(LevelArgs Af, const double *_
                                                    double *__restrict__ coarse,
                                                    double *__restrict__ coarseR, int *err) {
   using g = G<M>;
-  __shared__ double lds[g::TEAM_LDS];
-  Team<M> T;
-  T.init(lds, threadIdx.x);
+  __shared__ double lds[3 * g::CUBE + g::MISC];
+  Wave<M> W;
+  W.init(lds, threadIdx.x);
   const int cnx = Af.nx / 2;
   const int I = blockIdx.x % cnx, J = blockIdx.x / cnx;
   Cell<M> ch[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) load_cell<M>(recp<M>(Af, fine, 2 * I + (q & 1), 2 * J + (q >> 1)), T.S, ch[q]);
+  for (int q = 0; q < 4; ++q)
+    load_cell<M>(recp<M>(Af, fine, 2 * I + (q & 1), 2 * J + (q >> 1)), W.S, ch[q]);
   const double dsh = Af.ds, dsH = 4.0 * Af.ds;
   double mass = 0.0, m1 = 0.0, m2 = 0.0, en = 0.0;
 #pragma unroll
@@ -809,7 +983,7 @@ __global__ __launch_bounds__(WAVE) void k_restrict(LevelArgs Af, const double *_
   const double rhoH = mass / dsH, u1 = m1 / (rhoH * dsH), u2 = m2 / (rhoH * dsH);
   const double th = (en / dsH - rhoH * (u1 * u1 + u2 * u2)) / (3.0 * rhoH);
   if (!(rhoH > 0.0) || !(th > 0.0)) {
-    if (T.lane == 0) atomicOr(err, 1);
+    if (W.lane == 0) atomicOr(err, 1);
     return;
   }
   for (int pass = 0; pass < 2; ++pass) {
@@ -823,27 +997,27 @@ __global__ __launch_bounds__(WAVE) void k_restrict(LevelArgs Af, const double *_
     for (int q = 0; q < 4; ++q) {
       Cell<M> x;
       if (pass == 0) x = ch[q];
-      else load_cell<M>(recp<M>(Af, fineR, 2 * I + (q & 1), 2 * J + (q >> 1)), T.S, x);
-      put<M>(T.bX, T.S, x.f);
+      else load_cell<M>(recp<M>(Af, fineR, 2 * I + (q & 1), 2 * J + (q >> 1)), W.S, x);
+      put<M>(W.bX, W.S, x.f);
       wsync();
       double t[g::SL];
-      bchange<M>(T.bX, T.bA, T.bB, u1 - x.u1, u2 - x.u2, th - x.th, T.S, t);
+      bchange<M>(W.bX, W.bA, W.bB, u1 - x.u1, u2 - x.u2, th - x.th, W.S, t);
 #pragma unroll
       for (int r = 0; r < g::SL; ++r) acc[r] += t[r] * dsh / dsH;
     }
-    put<M>(T.bA, T.S, acc);
+    put<M>(W.bA, W.S, acc);
     wsync();
     if (pass == 0) {  // state: exact constraints of eq. (10)
-      const double zz = -(T.bA[g::XX] + T.bA[g::YY]);
+      const double zz = -(W.bA[g::XX] + W.bA[g::YY]);
       wsync();
-      if (T.lane == 0) {
-        T.bA[g::E1] = 0.0;
-        T.bA[g::E2] = 0.0;
-        T.bA[g::ZZ] = zz;
+      if (W.lane == 0) {
+        W.bA[g::E1] = 0.0;
+        W.bA[g::E2] = 0.0;
+        W.bA[g::ZZ] = zz;
       }
       wsync();
     }
-    store_record<M>(dst + (size_t)blockIdx.x * g::STRIDE, u1, u2, th, T.bA, T.lane);
+    store_record<M>(dst + (size_t)blockIdx.x * g::STRIDE, u1, u2, th, W.bA, W.lane);
     wsync();
   }
 }
@@ -856,35 +1030,36 @@ __global__ __launch_bounds__(WAVE) void k_correct(LevelArgs Af, double *__restri
                                                   const double *__restrict__ cnew,
                                                   const double *__restrict__ cold, int *err) {
   using g = G<M>;
-  __shared__ double lds[g::TEAM_LDS];
-  Team<M> T;
-  T.init(lds, threadIdx.x);
+  __shared__ double lds[4 * g::CUBE + g::MISC];
+  Wave<M> W;
+  W.init(lds + g::CUBE, threadIdx.x);
+  double *bD = lds;
   const int cnx = Af.nx / 2;
   const int I = blockIdx.x % cnx, J = blockIdx.x / cnx;
   Cell<M> fn, fo;
-  load_cell<M>(cnew + (size_t)blockIdx.x * g::STRIDE, T.S, fn);
-  load_cell<M>(cold + (size_t)blockIdx.x * g::STRIDE, T.S, fo);
+  load_cell<M>(cnew + (size_t)blockIdx.x * g::STRIDE, W.S, fn);
+  load_cell<M>(cold + (size_t)blockIdx.x * g::STRIDE, W.S, fo);
   double delta[g::SL];
-  put<M>(T.bX, T.S, fn.f);
+  put<M>(W.bX, W.S, fn.f);
   wsync();
-  bchange<M>(T.bX, T.bA, T.bB, fo.u1 - fn.u1, fo.u2 - fn.u2, fo.th - fn.th, T.S, delta);
+  bchange<M>(W.bX, W.bA, W.bB, fo.u1 - fn.u1, fo.u2 - fn.u2, fo.th - fn.th, W.S, delta);
 #pragma unroll
   for (int r = 0; r < g::SL; ++r) delta[r] -= fo.f[r];
-  put<M>(T.bC, T.S, delta);  // bC is free in this kernel
+  put<M>(bD, W.S, delta);
   wsync();
 #pragma unroll 1
   for (int q = 0; q < 4; ++q) {
     double *rec = const_cast<double *>(recp<M>(Af, fine, 2 * I + (q & 1), 2 * J + (q >> 1)));
     Cell<M> x;
-    load_cell<M>(rec, T.S, x);
+    load_cell<M>(rec, W.S, x);
     double t[g::SL];
-    bchange<M>(T.bC, T.bA, T.bB, x.u1 - fo.u1, x.u2 - fo.u2, x.th - fo.th, T.S, t);
+    bchange<M>(bD, W.bA, W.bB, x.u1 - fo.u1, x.u2 - fo.u2, x.th - fo.th, W.S, t);
     double fs[g::SL];
 #pragma unroll
     for (int r = 0; r < g::SL; ++r) fs[r] = x.f[r] + t[r];
     Cell<M> nc;
-    if (normalise<M>(x, fs, T, nc)) store_record<M>(rec, nc.u1, nc.u2, nc.th, T.bA, T.lane);
-    else if (T.lane == 0) atomicOr(err, 2);
+    if (normalise<M>(x.u1, x.u2, x.th, fs, W, nc)) store_record<M>(rec, nc.u1, nc.u2, nc.th, W.bA, W.lane);
+    else if (W.lane == 0) atomicOr(err, 2);
     wsync();
   }
 }
@@ -957,12 +1132,46 @@ hipError_t launch_sweep_diag(int M, const LevelArgs &A, double *st, const double
   const int ncell = a1 - a0 + 1;
   if (ncell <= 0) return hipSuccess;
   NRXX_DISPATCH_M(M, {
+    constexpr int NW = TeamWidth<MM>::NW;
     if (A.order == 1)
-      hipLaunchKernelGGL((k_sweep_diag<MM, 1>), dim3(ncell), dim3(WAVE), 0, s, A, st, rhs, dir, t, a0, err);
+      hipLaunchKernelGGL((k_sweep_diag<MM, 1, NW>), dim3(ncell), dim3(NW * WAVE), 0, s, A, st, rhs, dir, t, a0, err);
     else
-      hipLaunchKernelGGL((k_sweep_diag<MM, 2>), dim3(ncell), dim3(WAVE), 0, s, A, st, rhs, dir, t, a0, err);
+      hipLaunchKernelGGL((k_sweep_diag<MM, 2, NW>), dim3(ncell), dim3(NW * WAVE), 0, s, A, st, rhs, dir, t, a0, err);
   });
   return hipGetLastError();
+}
+
+hipError_t launch_sweep_persist(int M, const LevelArgs &A, double *st, const double *rhs,
+                                int nsweep, unsigned dirs, int *cnt, int base, int *err,
+                                int *abort_flag, unsigned long long limit, hipStream_t s) {
+  NRXX_DISPATCH_M(M, {
+    constexpr int NW = TeamWidth<MM>::NW;
+    if (A.order == 1)
+      hipLaunchKernelGGL((k_sweep_persist<MM, 1, NW>), dim3(A.nx), dim3(NW * WAVE), 0, s, A, st, rhs, nsweep, dirs, cnt, base, err, abort_flag, limit);
+    else
+      hipLaunchKernelGGL((k_sweep_persist<MM, 2, NW>), dim3(A.nx), dim3(NW * WAVE), 0, s, A, st, rhs, nsweep, dirs, cnt, base, err, abort_flag, limit);
+  });
+  return hipGetLastError();
+}
+
+int persist_max_columns(int M, int order) {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (M) {
+#define NRXX_OCC(MM)                                                                              \
+    case MM: {                                                                                    \
+      constexpr int NW = TeamWidth<MM>::NW;                                                       \
+      e = order == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_persist<MM, 1, NW>, NW * WAVE, 0) \
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_persist<MM, 2, NW>, NW * WAVE, 0); \
+    } break;
+    NRXX_OCC(3) NRXX_OCC(4) NRXX_OCC(5) NRXX_OCC(6) NRXX_OCC(7) NRXX_OCC(8)
+#undef NRXX_OCC
+    default: return 0;
+  }
+  if (e != hipSuccess) return 0;
+  return per * ncu;
 }
 
 hipError_t launch_residual(int M, const LevelArgs &A, const double *st, const double *rhs,
@@ -970,10 +1179,18 @@ hipError_t launch_residual(int M, const LevelArgs &A, const double *st, const do
                            hipStream_t s) {
   const int ncell = A.nx * A.ny;
   NRXX_DISPATCH_M(M, {
-    if (A.order == 1)
-      hipLaunchKernelGGL((k_residual<MM, 1>), dim3(ncell), dim3(WAVE), 0, s, A, st, rhs, Radd, out, norm_part, mode);
-    else
-      hipLaunchKernelGGL((k_residual<MM, 2>), dim3(ncell), dim3(WAVE), 0, s, A, st, rhs, Radd, out, norm_part, mode);
+    constexpr int NW = TeamWidth<MM>::NW;
+    if (mode == 0) {
+      if (A.order == 1)
+        hipLaunchKernelGGL((k_residual<MM, 1, NW, MODE_DEFECT>), dim3(ncell), dim3(NW * WAVE), 0, s, A, st, rhs, Radd, out, norm_part);
+      else
+        hipLaunchKernelGGL((k_residual<MM, 2, NW, MODE_DEFECT>), dim3(ncell), dim3(NW * WAVE), 0, s, A, st, rhs, Radd, out, norm_part);
+    } else {
+      if (A.order == 1)
+        hipLaunchKernelGGL((k_residual<MM, 1, NW, MODE_FAS>), dim3(ncell), dim3(NW * WAVE), 0, s, A, st, rhs, Radd, out, norm_part);
+      else
+        hipLaunchKernelGGL((k_residual<MM, 2, NW, MODE_FAS>), dim3(ncell), dim3(NW * WAVE), 0, s, A, st, rhs, Radd, out, norm_part);
+    }
   });
   return hipGetLastError();
 }

@@ -39,6 +39,12 @@ WORKLOADS = {
     # minmod, lid (0.5, 0, 0), 4-level V-cycle, residual 1e-10
     "lid128_shakhov_m5": dict(nx=128, ny=128, M=5, collision=1, Pr=2.0 / 3.0, Kn=0.075, order=2,
                               limiter=0, wall_u=[0.0, 0.0, 0.5, 0.0], levels=4, tol=1e-10),
+    # the same cavity with the paper's unlimited central slopes (eq. (15)):
+    # with minmod the residual of this case stalls near 5e-6 (limiter
+    # switching), so time-to-residual is measured on this variant
+    "lid128_shakhov_m5_central": dict(nx=128, ny=128, M=5, collision=1, Pr=2.0 / 3.0, Kn=0.075,
+                                      order=2, limiter=1, wall_u=[0.0, 0.0, 0.5, 0.0], levels=4,
+                                      tol=1e-10),
     # bottom-heated cavity: 256x256, Shakhov, Kn 0.05 or 0.2, M = 8, 2nd
     # order, bottom wall theta 2, others 1, static, 5-level V-cycle
     "heated256_shakhov_m8_kn005": dict(nx=256, ny=256, M=8, collision=1, Pr=2.0 / 3.0, Kn=0.05,

@@ -44,6 +44,7 @@ EXPORTS = {
     "nrxx_destroy": (c_int, [c_void_p]),
     "nrxx_last_error": (ctypes.c_char_p, [c_void_p]),
     "nrxx_level_shape": (c_int, [c_void_p, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
+    "nrxx_level_schedule": (c_int, [c_void_p, c_int]),
     "nrxx_init_maxwellian": (c_int, [c_void_p, c_int, c_void_p, c_double, c_double, c_double, c_double]),
     "nrxx_residual": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double)]),
     "nrxx_sweep": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_int, c_int]),
@@ -147,6 +148,11 @@ class Context:
         nx, ny = c_int(), c_int()
         self._chk(load().nrxx_level_shape(self.h, level, ctypes.byref(nx), ctypes.byref(ny)))
         return nx.value, ny.value
+
+    def level_schedule(self, level):
+        rc = load().nrxx_level_schedule(self.h, level)
+        self._chk(rc if rc < 0 else 0)
+        return rc
 
     def empty(self, level=0):
         nx, ny = self.level_shape(level)
