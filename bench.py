@@ -20,6 +20,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "smoother cell-moment updates/s + time-to-residual 1e-8, plain vs mixed/learned"
+KERNEL_SRC = os.path.join(ROOT, "paper_2206_13164_amd", "csrc", "nrxx_kernels.hip")
+PROFILES = os.path.join(ROOT, "profiles")
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
@@ -54,6 +56,25 @@ def cycle_accounting(spec):
     return tot
 
 
+def profiled_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    FETCH_SIZE / WRITE_SIZE summary, or None when the summary is missing or
+    was taken on a different kernel source."""
+    import hashlib
+    path = os.path.join(PROFILES, f"{kernel}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if vals.get("kernel_source_sha256") != src or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(spec, seconds_hint: float):
     """The oracle (FP64, serial paper-order sweeps, one thread) on a bounded
     sample: one V-cycle of the same workload from the Maxwellian start."""
@@ -81,6 +102,8 @@ def main():
     ap.add_argument("--workload", default="lid128_shakhov_m5_central")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-cycles", type=int, default=200)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device copy of this many bytes (counter calibration)")
     ap.add_argument("--schedule", type=int, default=0,
                     help="sweep schedule: 0 automatic, 1 per-diagonal launches, 2 persistent")
     args = ap.parse_args()
@@ -93,6 +116,16 @@ def main():
     import torch
     from paper_2206_13164_amd import inputs as I
     from paper_2206_13164_amd import nrxx as N
+
+    if args.copy_bytes:
+        # plain copy of a known size: reads and writes copy_bytes each
+        src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_bytes}))
+        return
 
     spec = I.spec(args.workload, schedule=args.schedule)
     tol = spec["tol"]
@@ -112,6 +145,7 @@ def main():
         rc, cyc, hist = one_solve()
         ref = hist[0]
     ctx.sweep_stats(reset=True)
+    sched = ctx.level_schedule(0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     cycles = []
@@ -122,18 +156,19 @@ def main():
             raise SystemExit(f"solve did not converge: rc={rc} cycles={cyc} last={hist[-1]:.3e}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    sweep_ms, sweep_cells = ctx.sweep_stats(reset=True)
+    sweep_ms, sweep_cells, launches = ctx.sweep_stats(reset=True)
     wall = t1 - t0
     acc = cycle_accounting(spec)
     ncyc = sum(cycles)
     assert abs(sweep_cells - ncyc * acc["cells"]) < 0.5, (sweep_cells, ncyc * acc["cells"])
     value = sweep_cells * NA / wall
-    launches = ncyc * acc["launches"]
     avg_launch_s = sweep_ms * 1e-3 / launches
     flops_per_launch = ncyc * acc["flops"] / launches
     bytes_per_launch = ncyc * acc["bytes"] / launches
     achieved_tflops = flops_per_launch / avg_launch_s / 1e12
     achieved_gbs = bytes_per_launch / avg_launch_s / 1e9
+    kname = "k_sweep_persist" if sched == 2 else "k_sweep_diag"
+    traffic = profiled_traffic(kname, args.workload)
 
     out = {
         "metric": METRIC,
@@ -165,8 +200,10 @@ def main():
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / PEAK_FP64_TFLOPS,
-            "traffic": None,
-            "kernel": "k_sweep_diag (one anti-diagonal of one sweep direction per launch)",
+            "traffic": traffic,
+            "kernel": kname + (" (persistent: up to 16 directional sweeps of one level per launch)"
+                               if sched == 2 else " (one anti-diagonal of one sweep direction per launch)"),
+            "launches": launches,
             "avg_launch_us": avg_launch_s * 1e6,
             "flops_per_launch": flops_per_launch,
             "bytes_per_launch": bytes_per_launch,

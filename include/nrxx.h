@@ -179,10 +179,12 @@ int nrxx_fas_vcycle(nrxx_ctx *ctx, double *state, double *norm_out);
 int nrxx_solve(nrxx_ctx *ctx, double *state, double tol, int max_cycles, double ref_norm,
                int *cycles_out, double *hist_out);
 
-/* Cumulative device time (ms, from HIP events) spent in sweep kernels and the
- * number of cell updates they made since the context was created or last
- * reset; `reset` != 0 zeroes both after reading.  Synchronises. */
-int nrxx_sweep_stats(nrxx_ctx *ctx, double *ms_out, double *cell_updates_out, int reset);
+/* Cumulative device time (ms, from HIP events recorded around each group of
+ * sweep kernels), the number of cell updates and the number of sweep kernel
+ * launches since the context was created or last reset; any output may be
+ * NULL; `reset` != 0 zeroes the counts after reading.  Synchronises. */
+int nrxx_sweep_stats(nrxx_ctx *ctx, double *ms_out, double *cell_updates_out,
+                     double *launches_out, int reset);
 
 #ifdef __cplusplus
 }

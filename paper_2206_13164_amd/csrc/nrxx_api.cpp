@@ -85,9 +85,9 @@ struct nrxx_ctx {
   std::vector<long long> pbase;          // per level: counter value at the next launch
   std::vector<int> persist;              // per level: 1 = persistent sweeps
   std::string err;
-  struct Timed { hipEvent_t a, b; double cells; };
+  struct Timed { hipEvent_t a, b; double cells, launches; };
   std::vector<Timed> timed;
-  double sweep_ms = 0.0, sweep_cells = 0.0;
+  double sweep_ms = 0.0, sweep_cells = 0.0, sweep_launches = 0.0;
 };
 
 namespace {
@@ -156,6 +156,7 @@ int sweep_impl(nrxx_ctx *c, int level, double *st, const double *rhs, int mask, 
     for (int k = 0; k < 4; ++k)
       if (mask & (1 << k)) dirs.push_back(k);
   ndir = (int)dirs.size();
+  double launches = 0.0;
   if (c->persist[level]) {
     // up to 16 directional sweeps per launch (2 bits per direction)
     for (size_t s0 = 0; s0 < dirs.size(); s0 += 16) {
@@ -169,14 +170,18 @@ int sweep_impl(nrxx_ctx *c, int level, double *st, const double *rhs, int mask, 
       CHK(launch_sweep_persist(c->M, A, st, rhs, nsw, bits, c->cnt[level], (int)c->pbase[level],
                                c->derr, c->dabort, 200000000ULL /* 2 s */, c->stream));
       c->pbase[level] += (long long)nsw * A.ny;
+      launches += 1.0;
     }
   } else {
     for (int k : dirs)
-      for (int t = 0; t <= A.nx + A.ny - 2; ++t)
+      for (int t = 0; t <= A.nx + A.ny - 2; ++t) {
         CHK(launch_sweep_diag(c->M, A, st, rhs, k, t, c->derr, c->stream));
+        launches += 1.0;
+      }
   }
   CHK(hipEventRecord(tm.b, c->stream));
   tm.cells = (double)ndir * A.nx * A.ny;
+  tm.launches = launches;
   c->timed.push_back(tm);
   if (c->timed.size() > 4096) {  // fold finished timings
     CHK(hipEventSynchronize(c->timed.back().b));
@@ -185,6 +190,7 @@ int sweep_impl(nrxx_ctx *c, int level, double *st, const double *rhs, int mask, 
       (void)hipEventElapsedTime(&ms, x.a, x.b);
       c->sweep_ms += ms;
       c->sweep_cells += x.cells;
+      c->sweep_launches += x.launches;
       (void)hipEventDestroy(x.a);
       (void)hipEventDestroy(x.b);
     }
@@ -497,7 +503,8 @@ int nrxx_solve(nrxx_ctx *c, double *state, double tol, int max_cycles, double re
   return nrm <= tol * ref_norm ? NRXX_OK : NRXX_EMAXIT;
 }
 
-int nrxx_sweep_stats(nrxx_ctx *c, double *ms_out, double *cells_out, int reset) {
+int nrxx_sweep_stats(nrxx_ctx *c, double *ms_out, double *cells_out, double *launches_out,
+                     int reset) {
   if (!c) return NRXX_EINVAL;
   CHK(hipStreamSynchronize(c->stream));
   for (auto &x : c->timed) {
@@ -505,13 +512,15 @@ int nrxx_sweep_stats(nrxx_ctx *c, double *ms_out, double *cells_out, int reset) 
     CHK(hipEventElapsedTime(&ms, x.a, x.b));
     c->sweep_ms += ms;
     c->sweep_cells += x.cells;
+    c->sweep_launches += x.launches;
     (void)hipEventDestroy(x.a);
     (void)hipEventDestroy(x.b);
   }
   c->timed.clear();
   if (ms_out) *ms_out = c->sweep_ms;
   if (cells_out) *cells_out = c->sweep_cells;
-  if (reset) c->sweep_ms = c->sweep_cells = 0.0;
+  if (launches_out) *launches_out = c->sweep_launches;
+  if (reset) c->sweep_ms = c->sweep_cells = c->sweep_launches = 0.0;
   return NRXX_OK;
 }
 

@@ -55,7 +55,8 @@ EXPORTS = {
     "nrxx_fas_vcycle": (c_int, [c_void_p, c_void_p, ctypes.POINTER(c_double)]),
     "nrxx_solve": (c_int, [c_void_p, c_void_p, c_double, c_int, c_double, ctypes.POINTER(c_int),
                            c_void_p]),
-    "nrxx_sweep_stats": (c_int, [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double), c_int]),
+    "nrxx_sweep_stats": (c_int, [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double),
+                                 ctypes.POINTER(c_double), c_int]),
 }
 
 _lib = None
@@ -211,6 +212,8 @@ class Context:
         return rc, cyc.value, hist[: cyc.value + 1]
 
     def sweep_stats(self, reset=False):
-        ms, cells = c_double(), c_double()
-        self._chk(load().nrxx_sweep_stats(self.h, ctypes.byref(ms), ctypes.byref(cells), int(reset)))
-        return ms.value, cells.value
+        """(device ms in sweep kernels, cell updates, sweep kernel launches)."""
+        ms, cells, launches = c_double(), c_double(), c_double()
+        self._chk(load().nrxx_sweep_stats(self.h, ctypes.byref(ms), ctypes.byref(cells),
+                                          ctypes.byref(launches), int(reset)))
+        return ms.value, cells.value, launches.value
