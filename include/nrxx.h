@@ -86,7 +86,14 @@ typedef struct {
   int32_t s1, s2, s3;     /* pre-, post-smoothing and coarsest FS steps (Alg. 2) */
   int32_t gamma;          /* 1 = V-cycle, 2 = W-cycle */
   double mass0;           /* > 0: total mass restored after every cycle (Sec. 4); <= 0: off */
-  int32_t precision;      /* 0 = FP64 throughout (the only value accepted) */
+  int32_t precision;      /* 0 = FP64 throughout.  1 = FP32 smoothing blocks with FP64 defect
+                             correction: each block computes d = r - R(f) in FP64, runs its
+                             fast-sweeping steps in FP32 on the scaled problem
+                             R32(g) = R32(g0) + s d (g0 = fp32(f), s >= 1 chosen so that g - g0
+                             stays near 1e-2 of the level's first correction), and adds
+                             (g - g0) / s to f in FP64; residuals, restriction, coarse
+                             right-hand sides, corrections and the mass fix stay FP64, so the
+                             fixed point is the FP64 steady state.  Other values: NRXX_EINVAL. */
   int32_t schedule;       /* sweep schedule: 0 = automatic (persistent where the grid's columns
                              fit on the device at once), 1 = one launch per anti-diagonal,
                              2 = persistent on every level (NRXX_EINVAL if impossible) */
@@ -139,7 +146,10 @@ int nrxx_residual(nrxx_ctx *ctx, int level, const double *state, const double *r
  * cell's current state, f <- f + dt (R_ij(f) - r_ij), then re-expands the
  * cell in its new (u, theta) (Sec. 2.4).  The result equals the serial
  * cell-by-cell order of the paper exactly: cells are updated along the
- * anti-diagonals of each direction's order. */
+ * anti-diagonals of each direction's order.  With precision 1 the call is one
+ * FP32 smoothing block of `nsteps` steps (see nrxx_problem.precision); the
+ * block's scale reference is the defect of the context's first block on that
+ * level. */
 int nrxx_sweep(nrxx_ctx *ctx, int level, double *state, const double *rhs, int dir_mask, int nsteps);
 
 /* Restriction of Sec. 3.2.2: from level `level_fine` to level_fine + 1.

@@ -84,6 +84,12 @@ struct nrxx_ctx {
   std::vector<int *> cnt;                // per level: column progress counters
   std::vector<long long> pbase;          // per level: counter value at the next launch
   std::vector<int> persist;              // per level: 1 = persistent sweeps
+  std::vector<int> persist32;            // per level: 1 = persistent FP32 sweeps
+  // FP32 smoothing blocks (precision 1), per level: working copy g, its
+  // start g0, effective right-hand side r32, FP64 defect d64
+  std::vector<float *> g32, g0_32, r32;
+  std::vector<double *> d64;
+  double *dblk = nullptr;                // per level: block scale, reference defect norm
   std::string err;
   struct Timed { hipEvent_t a, b; double cells, launches; };
   std::vector<Timed> timed;
@@ -91,6 +97,10 @@ struct nrxx_ctx {
 };
 
 namespace {
+
+// Size of an FP32 block's unknowns' change relative to the level's first
+// correction (precision 1).
+constexpr double kBlockTau = 1e-2;
 
 int fail(nrxx_ctx *c, int code, const char *fmt, ...) {
   char buf[512];
@@ -199,6 +209,72 @@ int sweep_impl(nrxx_ctx *c, int level, double *st, const double *rhs, int mask, 
   return NRXX_OK;
 }
 
+// One FP32 smoothing block (precision 1).  The FP64 defect d = r - R64(f0)
+// is computed once; the sweeps run in FP32 on g (starting at g0 = fp32(f0))
+// for the right-hand side R32(g0) + s d, and (g - g0) / s is added to the FP64
+// state, which is re-expanded in FP64.  The fixed point of the FP32 sweeps
+// satisfies R32(g) - R32(g0) = s d, so (g - g0) / s approximates the Newton
+// correction J^-1 d; the scale s keeps g - g0 at about kBlockTau times the
+// level's first correction, so neither FP32 rounding of the state nor the
+// rounding noise of R32 (about 2^-24 of the flux terms) stops the FP64
+// defect from falling to FP64 levels, while s d stays small enough for the
+// nonlinearity of R to change the correction by only about that fraction.
+int sweep32_impl(nrxx_ctx *c, int level, double *st, const double *rhs, int mask, int nsteps) {
+  const LevelArgs &A = c->lv[level];
+  std::vector<int> dirs;
+  for (int s = 0; s < nsteps; ++s)
+    for (int k = 0; k < 4; ++k)
+      if (mask & (1 << k)) dirs.push_back(k);
+  if (dirs.empty()) return NRXX_OK;
+  nrxx_ctx::Timed tm;
+  CHK(hipEventCreate(&tm.a));
+  CHK(hipEventCreate(&tm.b));
+  CHK(hipEventRecord(tm.a, c->stream));
+  float *g = c->g32[level], *g0 = c->g0_32[level], *r = c->r32[level];
+  // d = r - R64(f0) and its norm; s = block scale; s d -> g as a temporary
+  // FP32 copy; r32 = R32(g0) + s d; then g = g0
+  double *scale = c->dblk + 2 * level;
+  CHK(launch_residual(c->M, A, st, rhs, nullptr, c->d64[level], c->partial, 0, c->stream));
+  CHK(launch_block_scale(A, c->partial, kBlockTau, scale + 1, scale, c->stream));
+  CHK(launch_to32(c->M, A, c->d64[level], g, nullptr, scale, c->stream));
+  CHK(launch_to32(c->M, A, st, g0, nullptr, nullptr, c->stream));
+  CHK(launch_fas32(c->M, A, g0, g, r, c->stream));
+  CHK(launch_to32(c->M, A, st, g, nullptr, nullptr, c->stream));
+  double launches = 0.0;
+  if (c->persist32[level]) {
+    for (size_t s0 = 0; s0 < dirs.size(); s0 += 16) {
+      const int nsw = (int)std::min<size_t>(16, dirs.size() - s0);
+      unsigned bits = 0;
+      for (int q = 0; q < nsw; ++q) bits |= (unsigned)dirs[s0 + q] << (2 * q);
+      if (c->pbase[level] + (long long)nsw * A.ny > (1LL << 30)) {
+        CHK(hipMemsetAsync(c->cnt[level], 0, sizeof(int) * A.nx, c->stream));
+        c->pbase[level] = 0;
+      }
+      CHK(launch_sweep_persist32(c->M, A, g, r, nsw, bits, c->cnt[level], (int)c->pbase[level],
+                                 c->derr, c->dabort, 200000000ULL, c->stream));
+      c->pbase[level] += (long long)nsw * A.ny;
+      launches += 1.0;
+    }
+  } else {
+    for (int k : dirs)
+      for (int t = 0; t <= A.nx + A.ny - 2; ++t) {
+        CHK(launch_sweep_diag32(c->M, A, g, r, k, t, c->derr, c->stream));
+        launches += 1.0;
+      }
+  }
+  CHK(launch_from32(c->M, A, st, g, g0, scale, c->derr, c->stream));
+  CHK(hipEventRecord(tm.b, c->stream));
+  tm.cells = (double)dirs.size() * A.nx * A.ny;
+  tm.launches = launches;
+  c->timed.push_back(tm);
+  return NRXX_OK;
+}
+
+int smooth_impl(nrxx_ctx *c, int level, double *st, const double *rhs, int mask, int nsteps) {
+  return c->P.precision == 1 ? sweep32_impl(c, level, st, rhs, mask, nsteps)
+                             : sweep_impl(c, level, st, rhs, mask, nsteps);
+}
+
 int residual_impl(nrxx_ctx *c, int level, const double *st, const double *rhs, double *out,
                   double *norm_out) {
   const LevelArgs &A = c->lv[level];
@@ -214,8 +290,8 @@ int residual_impl(nrxx_ctx *c, int level, const double *st, const double *rhs, d
 
 int vcycle_impl(nrxx_ctx *c, int k, double *st, const double *rhs) {
   const nrxx_problem &P = c->P;
-  if (k == c->L - 1) return sweep_impl(c, k, st, rhs, 15, P.s3);
-  int rc = sweep_impl(c, k, st, rhs, 15, P.s1);
+  if (k == c->L - 1) return smooth_impl(c, k, st, rhs, 15, P.s3);
+  int rc = smooth_impl(c, k, st, rhs, 15, P.s1);
   if (rc) return rc;
   const LevelArgs &A = c->lv[k];
   CHK(launch_residual(c->M, A, st, rhs, nullptr, c->Rbar[k], nullptr, 0, c->stream));
@@ -229,7 +305,7 @@ int vcycle_impl(nrxx_ctx *c, int k, double *st, const double *rhs) {
     if (rc) return rc;
   }
   CHK(launch_correct(c->M, A, st, c->ftil[k + 1], c->fbar[k + 1], c->derr, c->stream));
-  return sweep_impl(c, k, st, rhs, 15, P.s2);
+  return smooth_impl(c, k, st, rhs, 15, P.s2);
 }
 
 int mass_fix_impl(nrxx_ctx *c, double *st) {
@@ -266,7 +342,8 @@ int nrxx_create(const nrxx_problem *p, void *hip_stream, nrxx_ctx **out) {
     if (!(P.wall_theta[w] > 0)) return fail(nullptr, NRXX_EINVAL, "wall_theta[%d] <= 0", w);
   if (P.s1 < 0 || P.s2 < 0 || P.s3 < 0 || P.gamma < 1 || P.gamma > 2)
     return fail(nullptr, NRXX_EINVAL, "bad smoothing steps or gamma");
-  if (P.precision != 0) return fail(nullptr, NRXX_EINVAL, "precision = %d not supported", P.precision);
+  if (P.precision != 0 && P.precision != 1)
+    return fail(nullptr, NRXX_EINVAL, "precision = %d not supported", P.precision);
   if (P.schedule < 0 || P.schedule > 2) return fail(nullptr, NRXX_EINVAL, "schedule = %d", P.schedule);
   if ((long long)P.nx * P.ny > (1LL << 26)) return fail(nullptr, NRXX_EINVAL, "grid too large");
 
@@ -327,6 +404,22 @@ int nrxx_create(const nrxx_problem *p, void *hip_stream, nrxx_ctx **out) {
   c->cnt.assign(c->L, nullptr);
   c->pbase.assign(c->L, 0);
   c->persist.assign(c->L, 0);
+  c->persist32.assign(c->L, 0);
+  c->g32.assign(c->L, nullptr);
+  c->g0_32.assign(c->L, nullptr);
+  c->r32.assign(c->L, nullptr);
+  c->d64.assign(c->L, nullptr);
+  if (P.precision == 1) {
+    ok = ok && alloc(&c->dblk, 2 * (size_t)c->L);
+    if (ok) ok = hipMemsetAsync(c->dblk, 0, sizeof(double) * 2 * c->L, c->stream) == hipSuccess;
+  }
+  if (P.precision == 1)
+    for (int k = 0; k < c->L && ok; ++k) {
+      const size_t n = level_doubles(c, k);
+      ok = hipMalloc((void **)&c->g32[k], n * sizeof(float)) == hipSuccess &&
+           hipMalloc((void **)&c->g0_32[k], n * sizeof(float)) == hipSuccess &&
+           hipMalloc((void **)&c->r32[k], n * sizeof(float)) == hipSuccess && alloc(&c->d64[k], n);
+    }
   for (int k = 0; k < c->L && ok; ++k)
     ok = hipMalloc((void **)&c->cnt[k], sizeof(int) * c->lv[k].nx) == hipSuccess;
   ok = ok && hipHostMalloc((void **)&c->hscal, 16 * sizeof(double), hipHostMallocDefault) == hipSuccess;
@@ -345,8 +438,14 @@ int nrxx_create(const nrxx_problem *p, void *hip_stream, nrxx_ctx **out) {
   // sweep schedule per level: persistent (one workgroup per column, all
   // resident at once) or one launch per anti-diagonal
   const int maxcols = P.schedule == 1 ? 0 : persist_max_columns(P.M, P.order);
+  const int maxcols32 = (P.schedule == 1 || P.precision != 1) ? 0 : persist_max_columns32(P.M, P.order);
   for (int k = 0; k < c->L; ++k) {
     c->persist[k] = P.schedule != 1 && c->lv[k].nx <= maxcols;
+    c->persist32[k] = P.precision == 1 && P.schedule != 1 && c->lv[k].nx <= maxcols32;
+    if (P.schedule == 2 && P.precision == 1 && !c->persist32[k]) {
+      nrxx_destroy(c);
+      return fail(nullptr, NRXX_EINVAL, "persistent FP32 sweeps do not fit on the device");
+    }
     if (P.schedule == 2 && !c->persist[k]) {
       nrxx_destroy(c);
       return fail(nullptr, NRXX_EINVAL, "persistent sweeps need %d resident workgroups, device holds %d",
@@ -373,6 +472,12 @@ int nrxx_destroy(nrxx_ctx *c) {
   if (c->dabort) (void)hipFree(c->dabort);
   for (int *p : c->cnt)
     if (p) (void)hipFree(p);
+  for (auto *v : {&c->g32, &c->g0_32, &c->r32})
+    for (float *p : *v)
+      if (p) (void)hipFree(p);
+  for (double *p : c->d64)
+    if (p) (void)hipFree(p);
+  if (c->dblk) (void)hipFree(c->dblk);
   if (c->hscal) (void)hipHostFree(c->hscal);
   delete c;
   return NRXX_OK;
@@ -419,7 +524,7 @@ int nrxx_sweep(nrxx_ctx *c, int level, double *state, const double *rhs, int dir
   if (!c) return NRXX_EINVAL;
   if (!level_ok(c, level) || !state) return fail(c, NRXX_EINVAL, "bad level or NULL state");
   if (dir_mask < 0 || dir_mask > 15 || nsteps < 0) return fail(c, NRXX_EINVAL, "bad dir_mask or nsteps");
-  return sweep_impl(c, level, state, rhs, dir_mask, nsteps);
+  return smooth_impl(c, level, state, rhs, dir_mask, nsteps);
 }
 
 int nrxx_restrict(nrxx_ctx *c, int level_fine, const double *fine, const double *fineR,

@@ -37,6 +37,29 @@ hipError_t launch_sweep_persist(int M, const LevelArgs &A, double *st, const dou
 // Columns (workgroups) of the persistent sweep kernel that can be resident at
 // once on the current device (0 if unknown).
 int persist_max_columns(int M, int order);
+// FP32 smoothing blocks: sweeps on FP32 records, the effective FP32
+// right-hand side R32(g0) + d32 (k_residual in MODE_FAS), conversion of the
+// FP64 state to FP32 working copies and the FP64 write-back of the block's
+// increment.
+hipError_t launch_sweep_diag32(int M, const LevelArgs &A, float *st, const float *rhs, int dir,
+                               int t, int *err, hipStream_t s);
+hipError_t launch_sweep_persist32(int M, const LevelArgs &A, float *st, const float *rhs,
+                                  int nsweep, unsigned dirs, int *cnt, int base, int *err,
+                                  int *abort_flag, unsigned long long limit, hipStream_t s);
+int persist_max_columns32(int M, int order);
+hipError_t launch_fas32(int M, const LevelArgs &A, const float *g0, const float *d32, float *out,
+                        hipStream_t s);
+// g (and g0 if non-null) = fp32 copy of src, coefficients times *scale
+// (scale == nullptr: 1)
+hipError_t launch_to32(int M, const LevelArgs &A, const double *src, float *g, float *g0,
+                       const double *scale, hipStream_t s);
+// f0 <- normalise(f0 + (g - g0) / *scale), the difference formed in g0's basis
+hipError_t launch_from32(int M, const LevelArgs &A, double *f0, const float *g, const float *g0,
+                         const double *scale, int *err, hipStream_t s);
+// scale = max(1, tau dref / ||d||) from the per-cell weighted squares of d;
+// dref <- ||d|| when it is still zero
+hipError_t launch_block_scale(const LevelArgs &A, const double *part, double tau, double *dref,
+                              double *scale, hipStream_t s);
 hipError_t launch_residual(int M, const LevelArgs &A, const double *st, const double *rhs,
                            const double *Radd, double *out, double *norm_part, int mode,
                            hipStream_t s);

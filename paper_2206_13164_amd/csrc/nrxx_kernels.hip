@@ -177,13 +177,13 @@ struct Slots {
 };
 
 // Per-wavefront scratch and slot map.
-template <int M>
+template <typename Real, int M>
 struct Wave {
   using g = G<M>;
-  double *bX, *bA, *bB, *misc;
+  Real *bX, *bA, *bB, *misc;
   int lane;
   Slots<M> S;
-  __device__ __forceinline__ void init(double *base, int ln) {
+  __device__ __forceinline__ void init(Real *base, int ln) {
     bX = base;
     bA = base + g::CUBE;
     bB = base + 2 * g::CUBE;
@@ -194,59 +194,59 @@ struct Wave {
 };
 
 // Basis parameters (uniform) and the lane's coefficients of one record.
-template <int M>
+template <typename Real, int M>
 struct Cell {
-  double u1, u2, th;
-  double f[G<M>::SL];
+  Real u1, u2, th;
+  Real f[G<M>::SL];
 };
 
-template <int M>
-__device__ __forceinline__ void load_cell(const double *__restrict__ rec, const Slots<M> &S,
-                                          Cell<M> &c) {
+template <typename Real, int M>
+__device__ __forceinline__ void load_cell(const Real *__restrict__ rec, const Slots<M> &S,
+                                          Cell<Real, M> &c) {
   c.u1 = rec[0];
   c.u2 = rec[1];
   c.th = rec[2];
 #pragma unroll
-  for (int r = 0; r < G<M>::SL; ++r) c.f[r] = S.ok[r] ? rec[3 + S.ci[r]] : 0.0;
+  for (int r = 0; r < G<M>::SL; ++r) c.f[r] = S.ok[r] ? rec[3 + S.ci[r]] : Real(0.0);
 }
 
-template <int M>
-__device__ __forceinline__ void put(double *buf, const Slots<M> &S, const double (&v)[G<M>::SL]) {
+template <typename Real, int M>
+__device__ __forceinline__ void put(Real *buf, const Slots<M> &S, const Real (&v)[G<M>::SL]) {
 #pragma unroll
   for (int r = 0; r < G<M>::SL; ++r)
     if (S.ok[r]) buf[S.ca[r]] = v[r];
 }
 
-template <int M>
-__device__ __forceinline__ void put_slots(double *buf, int lane, const double (&v)[G<M>::SL]) {
+template <typename Real, int M>
+__device__ __forceinline__ void put_slots(Real *buf, int lane, const Real (&v)[G<M>::SL]) {
 #pragma unroll
   for (int r = 0; r < G<M>::SL; ++r) buf[lane + WAVE * r] = v[r];
 }
 
-template <int M>
-__device__ __forceinline__ void get_slots(const double *buf, int lane, double (&v)[G<M>::SL]) {
+template <typename Real, int M>
+__device__ __forceinline__ void get_slots(const Real *buf, int lane, Real (&v)[G<M>::SL]) {
 #pragma unroll
   for (int r = 0; r < G<M>::SL; ++r) v[r] = buf[lane + WAVE * r];
 }
 
 // Coalesced write of a full record from (params, LDS cube); odd-alpha_3
 // coefficients are written as zeros.
-template <int M>
-__device__ __forceinline__ void store_record(double *__restrict__ rec, double u1, double u2,
-                                             double th, const double *cube, int lane) {
+template <typename Real, int M>
+__device__ __forceinline__ void store_record(Real *__restrict__ rec, Real u1, Real u2,
+                                             Real th, const Real *cube, int lane) {
   using g = G<M>;
 #pragma unroll
   for (int t = 0; t < g::SR; ++t) {
     int v = lane + WAVE * t;
     if (v < g::NR) {
-      double x;
+      Real x;
       if (v == 0) x = u1;
       else if (v == 1) x = u2;
       else if (v == 2) x = th;
       else {
         int al = v - 3;
         int a1 = c_canon.a1[al], a2 = c_canon.a2[al], a3 = c_canon.a3[al];
-        x = (a3 & 1) ? 0.0 : cube[a1 + g::D1 * a2 + g::D2 * (a3 >> 1)];
+        x = (a3 & 1) ? Real(0.0) : cube[a1 + g::D1 * a2 + g::D2 * (a3 >> 1)];
       }
       rec[v] = x;
     }
@@ -258,13 +258,13 @@ __device__ __forceinline__ void store_record(double *__restrict__ rec, double u1
 // ---------------------------------------------------------------------------
 
 // Taylor coefficients of exp(-du t - dth t^2 / 2): the 1-D factors of the
-// exact re-expansion F_M^[u,th] -> F_M^[u+du, th+dth] (Sec. 2.3).
-template <int M>
-__device__ __forceinline__ void tcoef(double du, double dth, double (&c)[M + 1]) {
-  c[0] = 1.0;
+// exact re-expansion F_M^[u,th] -> F_M^[u+du, th+dth] (Sec. Real(2.3)).
+template <typename Real, int M>
+__device__ __forceinline__ void tcoef(Real du, Real dth, Real (&c)[M + 1]) {
+  c[0] = Real(1.0);
   c[1] = -du;
 #pragma unroll
-  for (int k = 1; k < M; ++k) c[k + 1] = (-du * c[k] - dth * c[k - 1]) * (1.0 / (k + 1));
+  for (int k = 1; k < M; ++k) c[k + 1] = (-du * c[k] - dth * c[k - 1]) * (Real(1.0) / (k + 1));
 }
 
 // res = T(in) for the basis change by (du1, du2, dth): three 1-D lower-
@@ -272,62 +272,62 @@ __device__ __forceinline__ void tcoef(double du, double dth, double (&c)[M + 1])
 // distinct LDS cubes; the result stays in registers.  Terms beyond alpha_d
 // read a valid address with a zero coefficient, so every LDS read of a pass
 // is issued at once (adding fma(0, x, acc) leaves acc unchanged).
-template <int M>
-__device__ __forceinline__ void bchange(const double *in, double *t1, double *t2, double du1,
-                                        double du2, double dth, const Slots<M> &S,
-                                        double (&res)[G<M>::SL]) {
+template <typename Real, int M>
+__device__ __forceinline__ void bchange(const Real *in, Real *t1, Real *t2, Real du1,
+                                        Real du2, Real dth, const Slots<M> &S,
+                                        Real (&res)[G<M>::SL]) {
   using g = G<M>;
-  double c[M + 1];
-  tcoef<M>(du1, dth, c);
+  Real c[M + 1];
+  tcoef<Real, M>(du1, dth, c);
 #pragma unroll
   for (int r = 0; r < g::SL; ++r) {
-    const double *p = in + S.ca[r];
-    double x[M + 1];
+    const Real *p = in + S.ca[r];
+    Real x[M + 1];
 #pragma unroll
     for (int k = 0; k <= M; ++k) x[k] = p[k <= S.a1[r] ? -k : 0];
-    double acc = x[0];
+    Real acc = x[0];
 #pragma unroll
-    for (int k = 1; k <= M; ++k) acc = fma(k <= S.a1[r] ? c[k] : 0.0, x[k], acc);
+    for (int k = 1; k <= M; ++k) acc = fma(k <= S.a1[r] ? c[k] : Real(0.0), x[k], acc);
     if (S.ok[r]) t1[S.ca[r]] = acc;
   }
   wsync();
-  tcoef<M>(du2, dth, c);
+  tcoef<Real, M>(du2, dth, c);
 #pragma unroll
   for (int r = 0; r < g::SL; ++r) {
-    const double *p = t1 + S.ca[r];
-    double x[M + 1];
+    const Real *p = t1 + S.ca[r];
+    Real x[M + 1];
 #pragma unroll
     for (int k = 0; k <= M; ++k) x[k] = p[k <= S.a2[r] ? -k * g::D1 : 0];
-    double acc = x[0];
+    Real acc = x[0];
 #pragma unroll
-    for (int k = 1; k <= M; ++k) acc = fma(k <= S.a2[r] ? c[k] : 0.0, x[k], acc);
+    for (int k = 1; k <= M; ++k) acc = fma(k <= S.a2[r] ? c[k] : Real(0.0), x[k], acc);
     if (S.ok[r]) t2[S.ca[r]] = acc;
   }
   wsync();
-  tcoef<M>(0.0, dth, c);  // u_3 = 0 on both sides: only even powers survive
+  tcoef<Real, M>(Real(0.0), dth, c);  // u_3 = 0 on both sides: only even powers survive
 #pragma unroll
   for (int r = 0; r < g::SL; ++r) {
-    const double *p = t2 + S.ca[r];
-    double x[M / 2 + 1];
+    const Real *p = t2 + S.ca[r];
+    Real x[M / 2 + 1];
 #pragma unroll
     for (int k = 0; 2 * k <= M; ++k) x[k] = p[k <= S.m[r] ? -k * g::D2 : 0];
-    double acc = x[0];
+    Real acc = x[0];
 #pragma unroll
-    for (int k = 1; 2 * k <= M; ++k) acc = fma(k <= S.m[r] ? c[2 * k] : 0.0, x[k], acc);
-    res[r] = S.ok[r] ? acc : 0.0;
+    for (int k = 1; 2 * k <= M; ++k) acc = fma(k <= S.m[r] ? c[2 * k] : Real(0.0), x[k], acc);
+    res[r] = S.ok[r] ? acc : Real(0.0);
   }
   wsync();
 }
 
 // (Pi_M xi_d f)_alpha = th f_{alpha-e_d} + u_d f_alpha + (alpha_d+1) f_{alpha+e_d}
-template <int M>
-__device__ __forceinline__ double ximul(int D, const double *f, double ud, double th,
+template <typename Real, int M>
+__device__ __forceinline__ Real ximul(int D, const Real *f, Real ud, Real th,
                                         const Slots<M> &S, int r) {
   const int st = D == 0 ? 1 : G<M>::D1;
-  const double *p = f + S.ca[r];
+  const Real *p = f + S.ca[r];
   const int ad = D == 0 ? S.a1[r] : S.a2[r];
-  const double x0 = p[0], xl = p[ad >= 1 ? -st : 0], xh = p[S.n[r] < M ? st : 0];
-  double v = ud * x0;
+  const Real x0 = p[0], xl = p[ad >= 1 ? -st : 0], xh = p[S.n[r] < M ? st : 0];
+  Real v = ud * x0;
   if (ad >= 1) v += th * xl;
   if (S.n[r] < M) v += (ad + 1) * xh;
   return v;
@@ -336,40 +336,43 @@ __device__ __forceinline__ double ximul(int D, const double *f, double ud, doubl
 // Regularisation term of direction D at |beta| = M (zero below):
 // (beta_D + 1) [sum_k f_{b+e_D-e_k} du_k + 1/2 sum_k f_{b+e_D-2e_k} dth],
 // du_3 = 0, taken of (fL + fR) / 2 (fR may equal fL for the in-cell term).
-template <int M>
-__device__ __forceinline__ double regul(int D, const double *fL, const double *fR, double du1,
-                                        double du2, double dth, const Slots<M> &S, int r) {
+template <typename Real, int M>
+__device__ __forceinline__ Real regul(int D, const Real *fL, const Real *fR, Real du1,
+                                        Real du2, Real dth, const Slots<M> &S, int r) {
   using g = G<M>;
-  if (!S.ok[r] || S.n[r] != M) return 0.0;
+  if (!S.ok[r] || S.n[r] != M) return Real(0.0);
   const int base = S.ca[r] + (D == 0 ? 1 : g::D1);  // b + e_D
   const int b0 = S.a1[r] + (D == 0), b1 = S.a2[r] + (D == 1), b2 = 2 * S.m[r];
-  double acc = 0.0;
-  if (b0 >= 1) acc += 0.5 * (fL[base - 1] + fR[base - 1]) * du1;
-  if (b0 >= 2) acc += 0.5 * (0.5 * (fL[base - 2] + fR[base - 2])) * dth;
-  if (b1 >= 1) acc += 0.5 * (fL[base - g::D1] + fR[base - g::D1]) * du2;
-  if (b1 >= 2) acc += 0.5 * (0.5 * (fL[base - 2 * g::D1] + fR[base - 2 * g::D1])) * dth;
+  Real acc = Real(0.0);
+  if (b0 >= 1) acc += Real(0.5) * (fL[base - 1] + fR[base - 1]) * du1;
+  if (b0 >= 2) acc += Real(0.5) * (Real(0.5) * (fL[base - 2] + fR[base - 2])) * dth;
+  if (b1 >= 1) acc += Real(0.5) * (fL[base - g::D1] + fR[base - g::D1]) * du2;
+  if (b1 >= 2) acc += Real(0.5) * (Real(0.5) * (fL[base - 2 * g::D1] + fR[base - 2 * g::D1])) * dth;
   // k = 3: du_3 = 0, and b - e_3 has odd alpha_3
-  if (b2 >= 2) acc += 0.5 * (0.5 * (fL[base - g::D2] + fR[base - g::D2])) * dth;
+  if (b2 >= 2) acc += Real(0.5) * (Real(0.5) * (fL[base - g::D2] + fR[base - g::D2])) * dth;
   const int bd = D == 0 ? S.a1[r] : S.a2[r];
   return (bd + 1) * acc;
 }
 
-__device__ __forceinline__ double minmod(double a, double b) {
-  if (a > 0.0 && b > 0.0) return fmin(a, b);
-  if (a < 0.0 && b < 0.0) return fmax(a, b);
-  return 0.0;
+template <typename Real>
+__device__ __forceinline__ Real minmod(Real a, Real b) {
+  if (a > Real(0.0) && b > Real(0.0)) return fmin(a, b);
+  if (a < Real(0.0) && b < Real(0.0)) return fmax(a, b);
+  return Real(0.0);
 }
 
-__device__ __forceinline__ double limited(int limiter, double hi, double c, double lo) {
-  return limiter == 1 ? 0.5 * (hi - lo) : minmod(hi - c, c - lo);
+template <typename Real>
+__device__ __forceinline__ Real limited(int limiter, Real hi, Real c, Real lo) {
+  return limiter == 1 ? Real(0.5) * (hi - lo) : minmod<Real>(hi - c, c - lo);
 }
 
 // Probabilists' Hermite polynomial by recurrence.
-__device__ __forceinline__ double hermite(int n, double x) {
-  double h0 = 1.0, h1 = x;
-  if (n == 0) return 1.0;
+template <typename Real>
+__device__ __forceinline__ Real hermite(int n, Real x) {
+  Real h0 = Real(1.0), h1 = x;
+  if (n == 0) return Real(1.0);
   for (int k = 1; k < n; ++k) {
-    double h2 = x * h1 - k * h0;
+    Real h2 = x * h1 - k * h0;
     h0 = h1;
     h1 = h2;
   }
@@ -379,63 +382,64 @@ __device__ __forceinline__ double hermite(int n, double x) {
 // I_kl(a) = (2 pi)^-1/2 int_{-a}^inf He_k He_l e^{-w^2/2} dw from the
 // half-range moments K_n (in LDS) and He_k He_l = sum_j k! l! / (j! (k-j)!
 // (l-j)!) He_{k+l-2j}.
-__device__ __forceinline__ double halfI(const double *K, int k, int l) {
-  if (l < 0) return 0.0;
-  double acc = 0.0;
+template <typename Real>
+__device__ __forceinline__ Real halfI(const Real *K, int k, int l) {
+  if (l < 0) return Real(0.0);
+  Real acc = Real(0.0);
   int jm = k < l ? k : l;
   for (int j = 0; j <= jm; ++j)
-    acc += c_fact.v[k] * c_fact.v[l] * (c_fact.inv[j] * c_fact.inv[k - j] * c_fact.inv[l - j]) *
+    acc += Real(c_fact.v[k]) * Real(c_fact.v[l]) * (Real(c_fact.inv[j]) * Real(c_fact.inv[k - j]) * Real(c_fact.inv[l - j])) *
            K[k + l - 2 * j];
   return acc;
 }
 
 // Outward flux through a diffuse wall in the cell basis (reading of the
-// Maxwell boundary condition of Sec. 2.3 / Sec. 4): the leaving half-range
+// Maxwell boundary condition of Sec. Real(2.3) / Sec. 4): the leaving half-range
 // of the cell distribution plus the entering half of the wall Maxwellian,
 // whose density makes the net mass flux zero.  fc: the cell's coefficients
 // (LDS cube).
-template <int M>
-__device__ void wall_flux(const LevelArgs &A, int wall, double u1, double u2, double th,
-                          const double *fc, Wave<M> &W, double (&phi)[G<M>::SL]) {
+template <typename Real, int M>
+__device__ void wall_flux(const LevelArgs &A, int wall, Real u1, Real u2, Real th,
+                          const Real *fc, Wave<Real, M> &W, Real (&phi)[G<M>::SL]) {
   using g = G<M>;
   const Slots<M> &S = W.S;
   const int lane = W.lane;
   const int d = (wall == 0 || wall == 2) ? 1 : 0;
-  const double sig = (wall == 1 || wall == 2) ? 1.0 : -1.0;
-  const double sq = sqrt(th);
-  const double a = sig * (d == 0 ? u1 : u2) / sq;
-  double *K = W.misc + g::KOFF;
-  double *Jp = W.misc + g::JOFF;
-  double *bc = W.misc + g::BOFF;
+  const Real sig = (wall == 1 || wall == 2) ? Real(1.0) : -Real(1.0);
+  const Real sq = sqrt(th);
+  const Real a = sig * (d == 0 ? u1 : u2) / sq;
+  Real *K = W.misc + g::KOFF;
+  Real *Jp = W.misc + g::JOFF;
+  Real *bc = W.misc + g::BOFF;
   // K_n(a) = (2 pi)^-1/2 int_{-a}^inf He_n e^{-w^2/2}
   for (int n = lane; n <= 2 * M + 1; n += WAVE)
-    K[n] = n == 0 ? 0.5 * erfc(-a * M_SQRT1_2)
-                  : hermite(n - 1, -a) * exp(-0.5 * a * a) * (0.5 * M_2_SQRTPI * M_SQRT1_2);
+    K[n] = n == 0 ? Real(0.5) * erfc(-a * Real(M_SQRT1_2))
+                  : hermite<Real>(n - 1, -a) * exp(-Real(0.5) * a * a) * (Real(0.5) * Real(M_2_SQRTPI) * Real(M_SQRT1_2));
   wsync();
   // J+_kl(a) = a I_kl + I_{k,l+1} + l I_{k,l-1}
   for (int t = lane; t < (M + 1) * (M + 1); t += WAVE) {
     int k = t / (M + 1), l = t % (M + 1);
-    Jp[t] = a * halfI(K, k, l) + halfI(K, k, l + 1) + l * halfI(K, k, l - 1);
+    Jp[t] = a * halfI<Real>(K, k, l) + halfI<Real>(K, k, l + 1) + l * halfI<Real>(K, k, l - 1);
   }
   wsync();
   // leaving half: sum_{beta_d} f_beta th^{(a_d-b_d)/2} sqrt(th) sig^{a_d+b_d} J+_{a_d b_d} / a_d!
-  const double isq = 1.0 / sq;
+  const Real isq = Real(1.0) / sq;
   const int dst = d == 0 ? 1 : g::D1;
 #pragma unroll
   for (int r = 0; r < g::SL; ++r) {
-    double acc = 0.0;
+    Real acc = Real(0.0);
     if (S.ok[r]) {
       int ad = d == 0 ? S.a1[r] : S.a2[r];
       int at = (d == 0 ? S.a2[r] : S.a1[r]) + 2 * S.m[r];  // transverse degree
       int base = S.ca[r] - ad * dst;                      // alpha with alpha_d = 0
-      double pa = 1.0;
+      Real pa = Real(1.0);
       for (int q = 0; q < ad; ++q) pa *= sq;
-      const double ifa = c_fact.inv[ad];
-      double ib = 1.0;
+      const Real ifa = Real(c_fact.inv[ad]);
+      Real ib = Real(1.0);
 #pragma unroll
       for (int bd = 0; bd <= M; ++bd) {
         if (bd + at <= M) {
-          double sgn = ((ad + bd) & 1) ? sig : 1.0;
+          Real sgn = ((ad + bd) & 1) ? sig : Real(1.0);
           acc += fc[base + bd * dst] * (pa * ib) * sq * sgn * Jp[ad * (M + 1) + bd] * ifa;
         }
         ib *= isq;
@@ -446,88 +450,89 @@ __device__ void wall_flux(const LevelArgs &A, int wall, double u1, double u2, do
   // wall density from zero net mass flux; phi_0 lives in lane 0, slot 0
   if (lane == 0) bc[0] = phi[0];
   wsync();
-  const double thw = A.wall_th[wall], sqw = sqrt(thw);
-  const double rhow = bc[0] * sqrt(2.0 * M_PI / thw);
+  const Real thw = Real(A.wall_th[wall]), sqw = sqrt(thw);
+  const Real rhow = bc[0] * sqrt(Real(2.0) * Real(M_PI) / thw);
   // entering half in the wall basis: only alpha = k e_d is non-zero
 #pragma unroll
   for (int r = 0; r < g::SL; ++r)
-    if (S.ok[r]) W.bX[S.ca[r]] = 0.0;
+    if (S.ok[r]) W.bX[S.ca[r]] = Real(0.0);
   wsync();
   if (lane <= M) {
     int k = lane;
-    double pw = 1.0;
+    Real pw = Real(1.0);
     for (int q = 0; q < k; ++q) pw *= sqw;
-    double sgn = (k & 1) ? sig : 1.0;
-    W.bX[k * dst] = rhow * pw * sqw * sgn * A.jminus[k];
+    Real sgn = (k & 1) ? sig : Real(1.0);
+    W.bX[k * dst] = rhow * pw * sqw * sgn * Real(A.jminus[k]);
   }
   wsync();
-  const double uw1 = d == 1 ? A.wall_u[wall] : 0.0, uw2 = d == 0 ? A.wall_u[wall] : 0.0;
-  double t[g::SL];
-  bchange<M>(W.bX, W.bA, W.bB, u1 - uw1, u2 - uw2, th - thw, S, t);
+  const Real uw1 = d == 1 ? Real(A.wall_u[wall]) : Real(0.0), uw2 = d == 0 ? Real(A.wall_u[wall]) : Real(0.0);
+  Real t[g::SL];
+  bchange<Real, M>(W.bX, W.bA, W.bB, u1 - uw1, u2 - uw2, th - thw, S, t);
 #pragma unroll
   for (int r = 0; r < g::SL; ++r) phi[r] += t[r];
 }
 
 // Face state of `c` on side `side` of a direction (eq. (15)): every variable
 // v -> v + side/2 * limited slope; zero slope when `flat`.
-template <int M>
-__device__ __forceinline__ void face_state(const Cell<M> &c, const Cell<M> &hi, const Cell<M> &lo,
-                                           int limiter, bool flat, double side, Cell<M> &out) {
+template <typename Real, int M>
+__device__ __forceinline__ void face_state(const Cell<Real, M> &c, const Cell<Real, M> &hi, const Cell<Real, M> &lo,
+                                           int limiter, bool flat, Real side, Cell<Real, M> &out) {
   if (flat) {
     out = c;
     return;
   }
-  out.u1 = c.u1 + 0.5 * side * limited(limiter, hi.u1, c.u1, lo.u1);
-  out.u2 = c.u2 + 0.5 * side * limited(limiter, hi.u2, c.u2, lo.u2);
-  out.th = c.th + 0.5 * side * limited(limiter, hi.th, c.th, lo.th);
+  out.u1 = c.u1 + Real(0.5) * side * limited<Real>(limiter, hi.u1, c.u1, lo.u1);
+  out.u2 = c.u2 + Real(0.5) * side * limited<Real>(limiter, hi.u2, c.u2, lo.u2);
+  out.th = c.th + Real(0.5) * side * limited<Real>(limiter, hi.th, c.th, lo.th);
 #pragma unroll
   for (int r = 0; r < G<M>::SL; ++r)
-    out.f[r] = c.f[r] + 0.5 * side * limited(limiter, hi.f[r], c.f[r], lo.f[r]);
+    out.f[r] = c.f[r] + Real(0.5) * side * limited<Real>(limiter, hi.f[r], c.f[r], lo.f[r]);
 }
 
-// Local time step of eq. (18), capped so that nu dt <= nu_cap when nu_cap > 0.
-__device__ __forceinline__ double local_dt(const LevelArgs &A, double u1, double u2, double th,
-                                           double nu) {
-  const double sq = sqrt(th);
-  double dt = A.cfl / ((fabs(u1) + A.C * sq) * A.idx + (fabs(u2) + A.C * sq) * A.idy);
-  if (A.nu_cap > 0.0 && nu * dt > A.nu_cap) dt = A.nu_cap / nu;
+// Local time step of eq. (18), capped so that nu dt <= nu_cap when nu_cap > Real(0.)
+template <typename Real>
+__device__ __forceinline__ Real local_dt(const LevelArgs &A, Real u1, Real u2, Real th,
+                                           Real nu) {
+  const Real sq = sqrt(th);
+  Real dt = Real(A.cfl) / ((fabs(u1) + Real(A.C) * sq) * Real(A.idx) + (fabs(u2) + Real(A.C) * sq) * Real(A.idy));
+  if (Real(A.nu_cap) > Real(0.0) && nu * dt > Real(A.nu_cap)) dt = Real(A.nu_cap) / nu;
   return dt;
 }
 
-// Two-step update of Sec. 2.4: new (u, th) from the coefficients fs given in
+// Two-step update of Sec. Real(2.4): new (u, th) from the coefficients fs given in
 // the old basis (eq. (3)), re-expansion, and the exact constraints of
 // eq. (10).  Result left in cube W.bA and in out; false for rho <= 0,
 // th <= 0 or non-finite values.
-template <int M>
-__device__ bool normalise(double ou1, double ou2, double oth, const double (&fs)[G<M>::SL],
-                          Wave<M> &W, Cell<M> &out) {
+template <typename Real, int M>
+__device__ bool normalise(Real ou1, Real ou2, Real oth, const Real (&fs)[G<M>::SL],
+                          Wave<Real, M> &W, Cell<Real, M> &out) {
   using g = G<M>;
-  put<M>(W.bX, W.S, fs);
+  put<Real, M>(W.bX, W.S, fs);
   wsync();
-  const double rho = W.bX[0];
-  const double fe1 = W.bX[g::E1], fe2 = W.bX[g::E2];
-  const double tr = W.bX[g::XX] + W.bX[g::YY] + W.bX[g::ZZ];
-  const double irho = 1.0 / rho;
-  const double u1n = ou1 + fe1 * irho, u2n = ou2 + fe2 * irho;
-  const double thn = oth + (2.0 * tr - (fe1 * fe1 + fe2 * fe2) * irho) * (irho * (1.0 / 3.0));
-  bool okp = rho > 0.0 && thn > 0.0 && isfinite(rho) && isfinite(thn) && isfinite(u1n) &&
+  const Real rho = W.bX[0];
+  const Real fe1 = W.bX[g::E1], fe2 = W.bX[g::E2];
+  const Real tr = W.bX[g::XX] + W.bX[g::YY] + W.bX[g::ZZ];
+  const Real irho = Real(1.0) / rho;
+  const Real u1n = ou1 + fe1 * irho, u2n = ou2 + fe2 * irho;
+  const Real thn = oth + (Real(2.0) * tr - (fe1 * fe1 + fe2 * fe2) * irho) * (irho * (Real(1.0) / Real(3.0)));
+  bool okp = rho > Real(0.0) && thn > Real(0.0) && isfinite(rho) && isfinite(thn) && isfinite(u1n) &&
              isfinite(u2n);
   if (!okp) return false;  // uniform branch
-  double t[g::SL];
-  bchange<M>(W.bX, W.bA, W.bB, u1n - ou1, u2n - ou2, thn - oth, W.S, t);
-  put<M>(W.bA, W.S, t);
+  Real t[g::SL];
+  bchange<Real, M>(W.bX, W.bA, W.bB, u1n - ou1, u2n - ou2, thn - oth, W.S, t);
+  put<Real, M>(W.bA, W.S, t);
   wsync();
-  const double zz = -(W.bA[g::XX] + W.bA[g::YY]);
+  const Real zz = -(W.bA[g::XX] + W.bA[g::YY]);
   bool fin = true;
 #pragma unroll
   for (int r = 0; r < g::SL; ++r) {
     const int ca = W.S.ca[r];
-    if (ca == g::E1 || ca == g::E2) t[r] = 0.0;
+    if (ca == g::E1 || ca == g::E2) t[r] = Real(0.0);
     if (ca == g::ZZ) t[r] = zz;
     if (W.S.ok[r] && !isfinite(t[r])) fin = false;
   }
   wsync();
-  if (W.lane < 2) W.bA[W.lane == 0 ? g::E1 : g::E2] = 0.0;
+  if (W.lane < 2) W.bA[W.lane == 0 ? g::E1 : g::E2] = Real(0.0);
   if (W.lane == 0) W.bA[g::ZZ] = zz;
   wsync();
   out.u1 = u1n;
@@ -538,8 +543,8 @@ __device__ bool normalise(double ou1, double ou2, double oth, const double (&fs)
   return __ballot(!fin) == 0;
 }
 
-template <int M>
-__device__ __forceinline__ const double *recp(const LevelArgs &A, const double *st, int i, int j) {
+template <typename Real, int M>
+__device__ __forceinline__ const Real *recp(const LevelArgs &A, const Real *st, int i, int j) {
   return st + ((size_t)j * A.nx + i) * G<M>::STRIDE;
 }
 
@@ -552,7 +557,7 @@ enum { MODE_SWEEP = 0, MODE_DEFECT = 1, MODE_FAS = 2 };
 // Faces: 0 = E (+x), 1 = W (-x), 2 = N (+y), 3 = S (-y).  Item q = f + 4 s:
 // s = 0 the cell's own face state, s = 1 the neighbour's.
 __device__ __forceinline__ int face_dir(int f) { return f >> 1; }
-__device__ __forceinline__ double face_side(int f) { return (f & 1) ? -1.0 : 1.0; }
+__device__ __forceinline__ int face_side(int f) { return (f & 1) ? -1 : 1; }
 __device__ __forceinline__ int face_wall(int f) { return f == 0 ? 1 : f == 1 ? 3 : f == 2 ? 2 : 0; }
 
 // Evaluate cell (i, j) with a team of NW wavefronts and
@@ -561,30 +566,30 @@ __device__ __forceinline__ int face_wall(int f) { return f == 0 ? 1 : f == 1 ? 3
 //  MODE_FAS   : out = R(f) + Radd (coarse right-hand side of eq. (22)).
 // Every wavefront returns; the team's LDS may be reused after a barrier.
 // A non-physical update sets bit 0 of *err and leaves the cell unchanged.
-template <int M, int ORDER, int NW, int MODE>
-__device__ void cell_team(const LevelArgs &A, double *lds, double *__restrict__ st,
-                          const double *__restrict__ rhs, const double *__restrict__ Radd,
-                          double *__restrict__ out, double *__restrict__ norm_part, int i, int j,
+template <typename Real, int M, int ORDER, int NW, int MODE>
+__device__ void cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
+                          const Real *__restrict__ rhs, const Real *__restrict__ Radd,
+                          Real *__restrict__ out, Real *__restrict__ norm_part, int i, int j,
                           int *err) {
   using g = G<M>;
   using L = Lay<M, NW>;
   const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-  Wave<M> W;
+  Wave<Real, M> W;
   W.init(lds + L::W + wv * L::WSZ, lane);
   const Slots<M> &S = W.S;
-  double *bC = lds + L::C;
-  double *sc = lds + L::S;
+  Real *bC = lds + L::C;
+  Real *sc = lds + L::S;
   const int nx = A.nx, ny = A.ny;
   const int cellidx = j * nx + i;
 
   // ---- phase 0: face states of this wavefront's items -------------------
-  Cell<M> c;
-  load_cell<M>(recp<M>(A, st, i, j), S, c);
+  Cell<Real, M> c;
+  load_cell<Real, M>(recp<Real, M>(A, st, i, j), S, c);
   if (wv == NW - 1) {
-    put<M>(bC, S, c.f);
+    put<Real, M>(bC, S, c.f);
     // collision frequency of eq. (29); rho = f_0 sits in lane 0, slot 0
-    const double rho = __shfl(c.f[0], 0);
-    const double nu = A.beta * sqrt(M_PI / 2.0) * rho * pow(c.th, 1.0 - A.omega) / A.Kn;
+    const Real rho = __shfl(c.f[0], 0);
+    const Real nu = Real(A.beta) * sqrt(Real(M_PI) / Real(2.0)) * rho * pow(c.th, Real(1.0) - Real(A.omega)) / Real(A.Kn);
     if (lane == 0) {
       sc[L::SC] = c.u1;
       sc[L::SC + 1] = c.u2;
@@ -594,36 +599,36 @@ __device__ void cell_team(const LevelArgs &A, double *lds, double *__restrict__ 
   }
   for (int q = wv; q < 8; q += NW) {
     const int f = q & 3, s = q >> 2, D = face_dir(f);
-    const double side = face_side(f);
+    const Real side = (Real)face_side(f);
     const int k = D == 0 ? i : j, n = D == 0 ? nx : ny;
     const int sd = (int)side;
     const bool wall = (k + sd < 0) || (k + sd >= n);
-    Cell<M> X;
+    Cell<Real, M> X;
     if (s == 0) {
       const bool flat = ORDER == 1 || k == 0 || k == n - 1;
       if (flat) X = c;
       else {
-        Cell<M> hi, lo;
-        load_cell<M>(D == 0 ? recp<M>(A, st, i + 1, j) : recp<M>(A, st, i, j + 1), S, hi);
-        load_cell<M>(D == 0 ? recp<M>(A, st, i - 1, j) : recp<M>(A, st, i, j - 1), S, lo);
-        face_state<M>(c, hi, lo, A.limiter, false, side, X);
+        Cell<Real, M> hi, lo;
+        load_cell<Real, M>(D == 0 ? recp<Real, M>(A, st, i + 1, j) : recp<Real, M>(A, st, i, j + 1), S, hi);
+        load_cell<Real, M>(D == 0 ? recp<Real, M>(A, st, i - 1, j) : recp<Real, M>(A, st, i, j - 1), S, lo);
+        face_state<Real, M>(c, hi, lo, A.limiter, false, side, X);
       }
     } else {
       if (wall) continue;
       const int kn = k + sd;
       const bool nflat = ORDER == 1 || kn == 0 || kn == n - 1;
-      Cell<M> nb;
-      load_cell<M>(D == 0 ? recp<M>(A, st, i + sd, j) : recp<M>(A, st, i, j + sd), S, nb);
+      Cell<Real, M> nb;
+      load_cell<Real, M>(D == 0 ? recp<Real, M>(A, st, i + sd, j) : recp<Real, M>(A, st, i, j + sd), S, nb);
       if (nflat) X = nb;
       else {
-        Cell<M> far;
-        load_cell<M>(D == 0 ? recp<M>(A, st, i + 2 * sd, j) : recp<M>(A, st, i, j + 2 * sd), S, far);
+        Cell<Real, M> far;
+        load_cell<Real, M>(D == 0 ? recp<Real, M>(A, st, i + 2 * sd, j) : recp<Real, M>(A, st, i, j + 2 * sd), S, far);
         // neighbour's face on the cell's side: slope from (far, nb, c)
-        if (sd > 0) face_state<M>(nb, far, c, A.limiter, false, -side, X);
-        else face_state<M>(nb, c, far, A.limiter, false, -side, X);
+        if (sd > 0) face_state<Real, M>(nb, far, c, A.limiter, false, -side, X);
+        else face_state<Real, M>(nb, c, far, A.limiter, false, -side, X);
       }
     }
-    put<M>(lds + L::F + q * g::CUBE, S, X.f);
+    put<Real, M>(lds + L::F + q * g::CUBE, S, X.f);
     if (lane == 0) {
       sc[L::SP + 4 * q] = X.u1;
       sc[L::SP + 4 * q + 1] = X.u2;
@@ -635,202 +640,202 @@ __device__ void cell_team(const LevelArgs &A, double *lds, double *__restrict__ 
   // ---- phase 1: half-fluxes projected into the cell basis ---------------
   for (int q = wv; q < 8; q += NW) {
     const int f = q & 3, s = q >> 2, D = face_dir(f);
-    const double side = face_side(f);
+    const Real side = (Real)face_side(f);
     const int k = D == 0 ? i : j, n = D == 0 ? nx : ny;
     const int sd = (int)side;
     const bool wall = (k + sd < 0) || (k + sd >= n);
-    double T[g::SL];
+    Real T[g::SL];
     if (wall) {
       if (s == 1) continue;
-      wall_flux<M>(A, face_wall(f), c.u1, c.u2, c.th, bC, W, T);
-      put_slots<M>(lds + L::T + q * g::SLOT, lane, T);
+      wall_flux<Real, M>(A, face_wall(f), c.u1, c.u2, c.th, bC, W, T);
+      put_slots<Real, M>(lds + L::T + q * g::SLOT, lane, T);
       continue;
     }
     // L / R face states: the cell is left of its E and N faces
     const int qo = f, qn = f + 4;
     const int qL = sd > 0 ? qo : qn, qR = sd > 0 ? qn : qo;
-    const double uL = sc[L::SP + 4 * qL + D], thL = sc[L::SP + 4 * qL + 2];
-    const double uR = sc[L::SP + 4 * qR + D], thR = sc[L::SP + 4 * qR + 2];
-    const double cL = A.C * sqrt(thL), cR = A.C * sqrt(thR);
-    const double lamL = fmin(uL - cL, uR - cR);
-    const double lamR = fmax(uL + cL, uR + cR);
+    const Real uL = sc[L::SP + 4 * qL + D], thL = sc[L::SP + 4 * qL + 2];
+    const Real uR = sc[L::SP + 4 * qR + D], thR = sc[L::SP + 4 * qR + 2];
+    const Real cL = Real(A.C) * sqrt(thL), cR = Real(A.C) * sqrt(thR);
+    const Real lamL = fmin(uL - cL, uR - cR);
+    const Real lamR = fmax(uL + cL, uR + cR);
     int kase;
-    double wm, wp;
-    const double iden = 1.0 / (lamR - lamL);
-    if (lamL >= 0.0) { kase = 0; wm = 0.0; wp = 1.0; }
-    else if (lamR <= 0.0) { kase = 1; wm = 1.0; wp = 0.0; }
+    Real wm, wp;
+    const Real iden = Real(1.0) / (lamR - lamL);
+    if (lamL >= Real(0.0)) { kase = 0; wm = Real(0.0); wp = Real(1.0); }
+    else if (lamR <= Real(0.0)) { kase = 1; wm = Real(1.0); wp = Real(0.0); }
     else { kase = 2; wm = -lamL * iden; wp = lamR * iden; }
     const bool isL = q == qL;
-    const double *fx = lds + L::F + q * g::CUBE;
-    const double ux = sc[L::SP + 4 * q + D], thx = sc[L::SP + 4 * q + 2];
+    const Real *fx = lds + L::F + q * g::CUBE;
+    const Real ux = sc[L::SP + 4 * q + D], thx = sc[L::SP + 4 * q + 2];
     if ((isL && kase == 1) || (!isL && kase == 0)) {
 #pragma unroll
-      for (int r = 0; r < g::SL; ++r) T[r] = 0.0;
+      for (int r = 0; r < g::SL; ++r) T[r] = Real(0.0);
     } else {
-      double a[g::SL];
+      Real a[g::SL];
 #pragma unroll
       for (int r = 0; r < g::SL; ++r) {
-        const double Fx = S.ok[r] ? ximul<M>(D, fx, ux, thx, S, r) : 0.0;
-        const double fr = S.ok[r] ? fx[S.ca[r]] : 0.0;
+        const Real Fx = S.ok[r] ? ximul<Real, M>(D, fx, ux, thx, S, r) : Real(0.0);
+        const Real fr = S.ok[r] ? fx[S.ca[r]] : Real(0.0);
         if (kase != 2) a[r] = Fx;
         else if (isL) a[r] = (lamR * Fx - lamL * lamR * fr) * iden;
         else a[r] = (-lamL * Fx + lamL * lamR * fr) * iden;
       }
-      const double xu1 = sc[L::SP + 4 * q], xu2 = sc[L::SP + 4 * q + 1];
+      const Real xu1 = sc[L::SP + 4 * q], xu2 = sc[L::SP + 4 * q + 1];
       if (xu1 == c.u1 && xu2 == c.u2 && thx == c.th) {
 #pragma unroll
         for (int r = 0; r < g::SL; ++r) T[r] = a[r];
       } else {
-        put<M>(W.bX, S, a);
+        put<Real, M>(W.bX, S, a);
         wsync();
-        bchange<M>(W.bX, W.bA, W.bB, c.u1 - xu1, c.u2 - xu2, c.th - thx, S, T);
+        bchange<Real, M>(W.bX, W.bA, W.bB, c.u1 - xu1, c.u2 - xu2, c.th - thx, S, T);
       }
     }
-    put_slots<M>(lds + L::T + q * g::SLOT, lane, T);
+    put_slots<Real, M>(lds + L::T + q * g::SLOT, lane, T);
     if (s == 0) {
       // regularisation jump of the face, straight path from L to R
-      const double *fL = lds + L::F + qL * g::CUBE, *fR = lds + L::F + qR * g::CUBE;
-      const double du1 = sc[L::SP + 4 * qR] - sc[L::SP + 4 * qL];
-      const double du2 = sc[L::SP + 4 * qR + 1] - sc[L::SP + 4 * qL + 1];
-      const double dth = thR - thL;
-      double gr[g::SL];
+      const Real *fL = lds + L::F + qL * g::CUBE, *fR = lds + L::F + qR * g::CUBE;
+      const Real du1 = sc[L::SP + 4 * qR] - sc[L::SP + 4 * qL];
+      const Real du2 = sc[L::SP + 4 * qR + 1] - sc[L::SP + 4 * qL + 1];
+      const Real dth = thR - thL;
+      Real gr[g::SL];
 #pragma unroll
-      for (int r = 0; r < g::SL; ++r) gr[r] = regul<M>(D, fL, fR, du1, du2, dth, S, r);
-      put_slots<M>(lds + L::GR + f * g::SLOT, lane, gr);
+      for (int r = 0; r < g::SL; ++r) gr[r] = regul<Real, M>(D, fL, fR, du1, du2, dth, S, r);
+      put_slots<Real, M>(lds + L::GR + f * g::SLOT, lane, gr);
       if (lane == 0) sc[L::SW + f] = sd > 0 ? wm : wp;
     }
   }
   if (wv == NW - 1) {
     // cell-local terms on the last wavefront
-    const double rho = bC[0];
-    const double nu = sc[L::SNU];
-    double T[g::SL];
+    const Real rho = bC[0];
+    const Real nu = sc[L::SNU];
+    Real T[g::SL];
     // collision Q = nu (f^E - f), eq. (5), (29); Shakhov f^E from eq. (8)
-    double c1 = 0.0, c2 = 0.0;
+    Real c1 = Real(0.0), c2 = Real(0.0);
     if (A.collision == 1) {
-      const double q1 = 2.0 * bC[g::X3] + bC[g::X3] + bC[g::X1Y2] + bC[g::X1Z2];
-      const double q2 = 2.0 * bC[g::Y3] + bC[g::X2Y1] + bC[g::Y3] + bC[g::Y1Z2];
-      c1 = (1.0 - A.Pr) * q1 * 0.2;
-      c2 = (1.0 - A.Pr) * q2 * 0.2;
+      const Real q1 = Real(2.0) * bC[g::X3] + bC[g::X3] + bC[g::X1Y2] + bC[g::X1Z2];
+      const Real q2 = Real(2.0) * bC[g::Y3] + bC[g::X2Y1] + bC[g::Y3] + bC[g::Y1Z2];
+      c1 = (Real(1.0) - Real(A.Pr)) * q1 * Real(0.2);
+      c2 = (Real(1.0) - Real(A.Pr)) * q2 * Real(0.2);
     }
 #pragma unroll
     for (int r = 0; r < g::SL; ++r) {
       const int ca = S.ca[r];
-      double fE = ca == 0 ? rho : 0.0;
+      Real fE = ca == 0 ? rho : Real(0.0);
       if (ca == g::X3 || ca == g::X1Y2 || ca == g::X1Z2) fE += c1;
       if (ca == g::Y3 || ca == g::X2Y1 || ca == g::Y1Z2) fE += c2;
-      T[r] = S.ok[r] ? nu * (fE - c.f[r]) : 0.0;
+      T[r] = S.ok[r] ? nu * (fE - c.f[r]) : Real(0.0);
     }
-    put_slots<M>(lds + L::T + L::T_Q * g::SLOT, lane, T);
+    put_slots<Real, M>(lds + L::T + L::T_Q * g::SLOT, lane, T);
     if (ORDER == 2) {
       // in-cell regularisation: jump between the cell's own two face states
 #pragma unroll
       for (int D = 0; D < 2; ++D) {
         const int fp = 2 * D, fm = 2 * D + 1;
-        const double j1 = sc[L::SP + 4 * fp] - sc[L::SP + 4 * fm];
-        const double j2 = sc[L::SP + 4 * fp + 1] - sc[L::SP + 4 * fm + 1];
-        const double j3 = sc[L::SP + 4 * fp + 2] - sc[L::SP + 4 * fm + 2];
+        const Real j1 = sc[L::SP + 4 * fp] - sc[L::SP + 4 * fm];
+        const Real j2 = sc[L::SP + 4 * fp + 1] - sc[L::SP + 4 * fm + 1];
+        const Real j3 = sc[L::SP + 4 * fp + 2] - sc[L::SP + 4 * fm + 2];
 #pragma unroll
-        for (int r = 0; r < g::SL; ++r) T[r] = regul<M>(D, bC, bC, j1, j2, j3, S, r);
-        put_slots<M>(lds + L::T + (L::T_GX + D) * g::SLOT, lane, T);
+        for (int r = 0; r < g::SL; ++r) T[r] = regul<Real, M>(D, bC, bC, j1, j2, j3, S, r);
+        put_slots<Real, M>(lds + L::T + (L::T_GX + D) * g::SLOT, lane, T);
       }
     }
-    const double *rr = MODE == MODE_FAS ? Radd : rhs;
+    const Real *rr = MODE == MODE_FAS ? Radd : rhs;
     if (rr) {
       // right-hand side (Alg. 1) or the restricted residual (eq. (22)) in
       // the cell basis
-      Cell<M> r;
-      load_cell<M>(recp<M>(A, rr, i, j), S, r);
+      Cell<Real, M> r;
+      load_cell<Real, M>(recp<Real, M>(A, rr, i, j), S, r);
       if ((r.u1 == c.u1 && r.u2 == c.u2 && r.th == c.th) || MODE == MODE_FAS) {
 #pragma unroll
         for (int q = 0; q < g::SL; ++q) T[q] = r.f[q];
       } else {
-        put<M>(W.bX, S, r.f);
+        put<Real, M>(W.bX, S, r.f);
         wsync();
-        bchange<M>(W.bX, W.bA, W.bB, c.u1 - r.u1, c.u2 - r.u2, c.th - r.th, S, T);
+        bchange<Real, M>(W.bX, W.bA, W.bB, c.u1 - r.u1, c.u2 - r.u2, c.th - r.th, S, T);
       }
-      put_slots<M>(lds + L::T + L::T_RHS * g::SLOT, lane, T);
+      put_slots<Real, M>(lds + L::T + L::T_RHS * g::SLOT, lane, T);
     }
   }
   __syncthreads();
 
   // ---- phase 2 (wavefront 0): assemble R_ij in a fixed order ------------
   if (wv == 0) {
-    double R[g::SL];
+    Real R[g::SL];
 #pragma unroll
-    for (int r = 0; r < g::SL; ++r) R[r] = 0.0;
+    for (int r = 0; r < g::SL; ++r) R[r] = Real(0.0);
 #pragma unroll
     for (int D = 0; D < 2; ++D) {
       const int k = D == 0 ? i : j, n = D == 0 ? nx : ny;
-      const double ih = D == 0 ? A.idx : A.idy;
+      const Real ih = D == 0 ? Real(A.idx) : Real(A.idy);
 #pragma unroll
       for (int sdi = 0; sdi < 2; ++sdi) {
         const int f = 2 * D + sdi;
         const int sd = sdi == 0 ? 1 : -1;
-        double TL[g::SL], TR[g::SL];
+        Real TL[g::SL], TR[g::SL];
         if (k + sd < 0 || k + sd >= n) {
-          get_slots<M>(lds + L::T + f * g::SLOT, lane, TL);
+          get_slots<Real, M>(lds + L::T + f * g::SLOT, lane, TL);
 #pragma unroll
           for (int r = 0; r < g::SL; ++r) R[r] -= TL[r] * ih;
           continue;
         }
         const int qL = sd > 0 ? f : f + 4, qR = sd > 0 ? f + 4 : f;
-        double gr[g::SL];
-        get_slots<M>(lds + L::T + qL * g::SLOT, lane, TL);
-        get_slots<M>(lds + L::T + qR * g::SLOT, lane, TR);
-        get_slots<M>(lds + L::GR + f * g::SLOT, lane, gr);
-        const double w = sc[L::SW + f];
-        const double sgnF = sd > 0 ? -1.0 : 1.0;
+        Real gr[g::SL];
+        get_slots<Real, M>(lds + L::T + qL * g::SLOT, lane, TL);
+        get_slots<Real, M>(lds + L::T + qR * g::SLOT, lane, TR);
+        get_slots<Real, M>(lds + L::GR + f * g::SLOT, lane, gr);
+        const Real w = sc[L::SW + f];
+        const Real sgnF = sd > 0 ? -Real(1.0) : Real(1.0);
 #pragma unroll
         for (int r = 0; r < g::SL; ++r) R[r] += (sgnF * (TL[r] + TR[r]) + w * gr[r]) * ih;
       }
       if (ORDER == 2) {
-        double gc[g::SL];
-        get_slots<M>(lds + L::T + (L::T_GX + D) * g::SLOT, lane, gc);
+        Real gc[g::SL];
+        get_slots<Real, M>(lds + L::T + (L::T_GX + D) * g::SLOT, lane, gc);
 #pragma unroll
         for (int r = 0; r < g::SL; ++r) R[r] += gc[r] * ih;
       }
     }
     {
-      double q[g::SL];
-      get_slots<M>(lds + L::T + L::T_Q * g::SLOT, lane, q);
+      Real q[g::SL];
+      get_slots<Real, M>(lds + L::T + L::T_Q * g::SLOT, lane, q);
 #pragma unroll
       for (int r = 0; r < g::SL; ++r) R[r] += q[r];
     }
-    const double *rr = MODE == MODE_FAS ? Radd : rhs;
-    double rv[g::SL];
-    if (rr) get_slots<M>(lds + L::T + L::T_RHS * g::SLOT, lane, rv);
+    const Real *rr = MODE == MODE_FAS ? Radd : rhs;
+    Real rv[g::SL];
+    if (rr) get_slots<Real, M>(lds + L::T + L::T_RHS * g::SLOT, lane, rv);
     if (MODE == MODE_SWEEP) {
-      const double dt = local_dt(A, c.u1, c.u2, c.th, sc[L::SNU]);
-      double fs[g::SL];
+      const Real dt = local_dt<Real>(A, c.u1, c.u2, c.th, sc[L::SNU]);
+      Real fs[g::SL];
 #pragma unroll
       for (int r = 0; r < g::SL; ++r) fs[r] = c.f[r] + dt * (rr ? R[r] - rv[r] : R[r]);
-      Cell<M> nc;
-      if (normalise<M>(c.u1, c.u2, c.th, fs, W, nc))
-        store_record<M>(const_cast<double *>(recp<M>(A, st, i, j)), nc.u1, nc.u2, nc.th, W.bA, lane);
+      Cell<Real, M> nc;
+      if (normalise<Real, M>(c.u1, c.u2, c.th, fs, W, nc))
+        store_record<Real, M>(const_cast<Real *>(recp<Real, M>(A, st, i, j)), nc.u1, nc.u2, nc.th, W.bA, lane);
       else if (lane == 0)
         atomicOr(err, 1);
     } else {
-      double o[g::SL];
+      Real o[g::SL];
 #pragma unroll
       for (int r = 0; r < g::SL; ++r)
-        o[r] = MODE == MODE_FAS ? R[r] + rv[r] : (rr ? rv[r] : 0.0) - R[r];
+        o[r] = MODE == MODE_FAS ? R[r] + rv[r] : (rr ? rv[r] : Real(0.0)) - R[r];
       if (out) {
-        put<M>(W.bA, S, o);
+        put<Real, M>(W.bA, S, o);
         wsync();
-        store_record<M>(out + (size_t)cellidx * g::STRIDE, c.u1, c.u2, c.th, W.bA, lane);
+        store_record<Real, M>(out + (size_t)cellidx * g::STRIDE, c.u1, c.u2, c.th, W.bA, lane);
       }
       if (MODE == MODE_DEFECT && norm_part) {
-        double s2 = 0.0;
+        Real s2 = Real(0.0);
 #pragma unroll
         for (int q = 0; q < g::SL; ++q) {
           if (!S.ok[q]) continue;
-          const double w = c_fact.v[S.a1[q]] * c_fact.v[S.a2[q]] * c_fact.v[2 * S.m[q]];
-          s2 += w * pow(c.th, -(double)S.n[q]) * o[q] * o[q];
+          const Real w = Real(c_fact.v[S.a1[q]]) * Real(c_fact.v[S.a2[q]]) * Real(c_fact.v[2 * S.m[q]]);
+          s2 += w * pow(c.th, -(Real)S.n[q]) * o[q] * o[q];
         }
 #pragma unroll
         for (int off = WAVE / 2; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
-        if (lane == 0) norm_part[cellidx] = s2 * A.ds;
+        if (lane == 0) norm_part[cellidx] = s2 * Real(A.ds);
       }
     }
   }
@@ -849,20 +854,20 @@ struct TeamWidth {
 // Kernels
 // ---------------------------------------------------------------------------
 
-// One anti-diagonal t of sweep direction `dir` (0..3 = D1..D4 of Sec. 3.1):
+// One anti-diagonal t of sweep direction `dir` (0..3 = D1..D4 of Sec. Real(3.1)):
 // cell a of the diagonal is (a0 + blockIdx.x, t - a) in the direction's
 // coordinates.  Cells of one diagonal never read each other (cross-shaped
 // stencil of radius <= 2), earlier diagonals are already updated and later
 // ones are not: the serial Gauss-Seidel order of Alg. 1 exactly.
-template <int M, int ORDER, int NW>
-__global__ __launch_bounds__(NW * WAVE) void k_sweep_diag(LevelArgs A, double *__restrict__ st,
-                                                                const double *__restrict__ rhs,
+template <typename Real, int M, int ORDER, int NW>
+__global__ __launch_bounds__(NW * WAVE) void k_sweep_diag(LevelArgs A, Real *__restrict__ st,
+                                                                const Real *__restrict__ rhs,
                                                                 int dir, int t, int a0, int *err) {
-  __shared__ double lds[Lay<M, NW>::TOTAL];
+  __shared__ Real lds[Lay<M, NW>::TOTAL];
   const int a = a0 + blockIdx.x, b = t - a;
   const bool irev = dir == 1 || dir == 2, jrev = dir == 2 || dir == 3;
   const int i = irev ? A.nx - 1 - a : a, j = jrev ? A.ny - 1 - b : b;
-  cell_team<M, ORDER, NW, MODE_SWEEP>(A, lds, st, rhs, nullptr, nullptr, nullptr, i, j, err);
+  cell_team<Real, M, ORDER, NW, MODE_SWEEP>(A, lds, st, rhs, nullptr, nullptr, nullptr, i, j, err);
 }
 
 // Wait until *flag >= target (agent-scope acquire).  Bounded: gives up after
@@ -892,13 +897,13 @@ __device__ __forceinline__ bool wait_at_least(const int *flag, int target, int *
 // Progress counters only grow: column i has finished base + s * ny + b + 1
 // cells after row b of sweep s.  Every wait is bounded (abort flag + wall
 // clock), so the grid always drains.
-template <int M, int ORDER, int NW>
+template <typename Real, int M, int ORDER, int NW>
 __global__ __launch_bounds__(NW * WAVE) void k_sweep_persist(
-    LevelArgs A, double *__restrict__ st, const double *__restrict__ rhs, int nsweep,
+    LevelArgs A, Real *__restrict__ st, const Real *__restrict__ rhs, int nsweep,
     unsigned dirs, int *cnt, int base, int *err, int *abort_flag, unsigned long long limit) {
   using L = Lay<M, NW>;
-  __shared__ double lds[L::TOTAL];
-  double *sc = lds + L::S;
+  __shared__ Real lds[L::TOTAL];
+  Real *sc = lds + L::S;
   const int i = blockIdx.x;
   const int nx = A.nx, ny = A.ny;
   for (int s = 0; s < nsweep; ++s) {
@@ -922,14 +927,14 @@ __global__ __launch_bounds__(NW * WAVE) void k_sweep_persist(
             ok = wait_at_least(cnt + ii, sbase - ny + bp + 1, abort_flag, limit);
           }
         }
-        sc[L::SAB] = ok ? 0.0 : 1.0;
+        sc[L::SAB] = ok ? Real(0.0) : Real(1.0);
       }
       __syncthreads();
-      if (sc[L::SAB] != 0.0) {
+      if (sc[L::SAB] != Real(0.0)) {
         if (threadIdx.x == 0) atomicOr(err, 4);
         return;  // uniform across the team
       }
-      cell_team<M, ORDER, NW, MODE_SWEEP>(A, lds, st, rhs, nullptr, nullptr, nullptr, i, j, err);
+      cell_team<Real, M, ORDER, NW, MODE_SWEEP>(A, lds, st, rhs, nullptr, nullptr, nullptr, i, j, err);
       if (threadIdx.x == 0) {
         // wavefront 0 stored the cell; publish it (agent-scope release)
         __hip_atomic_store(cnt + i, sbase + b + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -941,15 +946,15 @@ __global__ __launch_bounds__(NW * WAVE) void k_sweep_persist(
 
 // Residual over all cells (MODE_DEFECT) or the coarse right-hand side
 // (MODE_FAS), one team per cell.
-template <int M, int ORDER, int NW, int MODE>
-__global__ __launch_bounds__(NW * WAVE) void k_residual(LevelArgs A, const double *__restrict__ st,
-                                                              const double *__restrict__ rhs,
-                                                              const double *__restrict__ Radd,
-                                                              double *__restrict__ out,
-                                                              double *__restrict__ norm_part) {
-  __shared__ double lds[Lay<M, NW>::TOTAL];
+template <typename Real, int M, int ORDER, int NW, int MODE>
+__global__ __launch_bounds__(NW * WAVE) void k_residual(LevelArgs A, const Real *__restrict__ st,
+                                                              const Real *__restrict__ rhs,
+                                                              const Real *__restrict__ Radd,
+                                                              Real *__restrict__ out,
+                                                              Real *__restrict__ norm_part) {
+  __shared__ Real lds[Lay<M, NW>::TOTAL];
   const int cell = blockIdx.x;
-  cell_team<M, ORDER, NW, MODE>(A, lds, const_cast<double *>(st), rhs, Radd, out, norm_part,
+  cell_team<Real, M, ORDER, NW, MODE>(A, lds, const_cast<Real *>(st), rhs, Radd, out, norm_part,
                                 cell % A.nx, cell / A.nx, nullptr);
 }
 
@@ -962,19 +967,19 @@ __global__ __launch_bounds__(WAVE) void k_restrict(LevelArgs Af, const double *_
                                                    double *__restrict__ coarseR, int *err) {
   using g = G<M>;
   __shared__ double lds[3 * g::CUBE + g::MISC];
-  Wave<M> W;
+  Wave<double, M> W;
   W.init(lds, threadIdx.x);
   const int cnx = Af.nx / 2;
   const int I = blockIdx.x % cnx, J = blockIdx.x / cnx;
-  Cell<M> ch[4];
+  Cell<double, M> ch[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q)
-    load_cell<M>(recp<M>(Af, fine, 2 * I + (q & 1), 2 * J + (q >> 1)), W.S, ch[q]);
+    load_cell<double, M>(recp<double, M>(Af, fine, 2 * I + (q & 1), 2 * J + (q >> 1)), W.S, ch[q]);
   const double dsh = Af.ds, dsH = 4.0 * Af.ds;
   double mass = 0.0, m1 = 0.0, m2 = 0.0, en = 0.0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const double rho = recp<M>(Af, fine, 2 * I + (q & 1), 2 * J + (q >> 1))[3];
+    const double rho = recp<double, M>(Af, fine, 2 * I + (q & 1), 2 * J + (q >> 1))[3];
     mass += rho * dsh;
     m1 += rho * ch[q].u1 * dsh;
     m2 += rho * ch[q].u2 * dsh;
@@ -995,17 +1000,17 @@ __global__ __launch_bounds__(WAVE) void k_restrict(LevelArgs Af, const double *_
     for (int r = 0; r < g::SL; ++r) acc[r] = 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      Cell<M> x;
+      Cell<double, M> x;
       if (pass == 0) x = ch[q];
-      else load_cell<M>(recp<M>(Af, fineR, 2 * I + (q & 1), 2 * J + (q >> 1)), W.S, x);
-      put<M>(W.bX, W.S, x.f);
+      else load_cell<double, M>(recp<double, M>(Af, fineR, 2 * I + (q & 1), 2 * J + (q >> 1)), W.S, x);
+      put<double, M>(W.bX, W.S, x.f);
       wsync();
       double t[g::SL];
-      bchange<M>(W.bX, W.bA, W.bB, u1 - x.u1, u2 - x.u2, th - x.th, W.S, t);
+      bchange<double, M>(W.bX, W.bA, W.bB, u1 - x.u1, u2 - x.u2, th - x.th, W.S, t);
 #pragma unroll
       for (int r = 0; r < g::SL; ++r) acc[r] += t[r] * dsh / dsH;
     }
-    put<M>(W.bA, W.S, acc);
+    put<double, M>(W.bA, W.S, acc);
     wsync();
     if (pass == 0) {  // state: exact constraints of eq. (10)
       const double zz = -(W.bA[g::XX] + W.bA[g::YY]);
@@ -1017,7 +1022,7 @@ __global__ __launch_bounds__(WAVE) void k_restrict(LevelArgs Af, const double *_
       }
       wsync();
     }
-    store_record<M>(dst + (size_t)blockIdx.x * g::STRIDE, u1, u2, th, W.bA, W.lane);
+    store_record<double, M>(dst + (size_t)blockIdx.x * g::STRIDE, u1, u2, th, W.bA, W.lane);
     wsync();
   }
 }
@@ -1031,37 +1036,105 @@ __global__ __launch_bounds__(WAVE) void k_correct(LevelArgs Af, double *__restri
                                                   const double *__restrict__ cold, int *err) {
   using g = G<M>;
   __shared__ double lds[4 * g::CUBE + g::MISC];
-  Wave<M> W;
+  Wave<double, M> W;
   W.init(lds + g::CUBE, threadIdx.x);
   double *bD = lds;
   const int cnx = Af.nx / 2;
   const int I = blockIdx.x % cnx, J = blockIdx.x / cnx;
-  Cell<M> fn, fo;
-  load_cell<M>(cnew + (size_t)blockIdx.x * g::STRIDE, W.S, fn);
-  load_cell<M>(cold + (size_t)blockIdx.x * g::STRIDE, W.S, fo);
+  Cell<double, M> fn, fo;
+  load_cell<double, M>(cnew + (size_t)blockIdx.x * g::STRIDE, W.S, fn);
+  load_cell<double, M>(cold + (size_t)blockIdx.x * g::STRIDE, W.S, fo);
   double delta[g::SL];
-  put<M>(W.bX, W.S, fn.f);
+  put<double, M>(W.bX, W.S, fn.f);
   wsync();
-  bchange<M>(W.bX, W.bA, W.bB, fo.u1 - fn.u1, fo.u2 - fn.u2, fo.th - fn.th, W.S, delta);
+  bchange<double, M>(W.bX, W.bA, W.bB, fo.u1 - fn.u1, fo.u2 - fn.u2, fo.th - fn.th, W.S, delta);
 #pragma unroll
   for (int r = 0; r < g::SL; ++r) delta[r] -= fo.f[r];
-  put<M>(bD, W.S, delta);
+  put<double, M>(bD, W.S, delta);
   wsync();
 #pragma unroll 1
   for (int q = 0; q < 4; ++q) {
-    double *rec = const_cast<double *>(recp<M>(Af, fine, 2 * I + (q & 1), 2 * J + (q >> 1)));
-    Cell<M> x;
-    load_cell<M>(rec, W.S, x);
+    double *rec = const_cast<double *>(recp<double, M>(Af, fine, 2 * I + (q & 1), 2 * J + (q >> 1)));
+    Cell<double, M> x;
+    load_cell<double, M>(rec, W.S, x);
     double t[g::SL];
-    bchange<M>(bD, W.bA, W.bB, x.u1 - fo.u1, x.u2 - fo.u2, x.th - fo.th, W.S, t);
+    bchange<double, M>(bD, W.bA, W.bB, x.u1 - fo.u1, x.u2 - fo.u2, x.th - fo.th, W.S, t);
     double fs[g::SL];
 #pragma unroll
     for (int r = 0; r < g::SL; ++r) fs[r] = x.f[r] + t[r];
-    Cell<M> nc;
-    if (normalise<M>(x.u1, x.u2, x.th, fs, W, nc)) store_record<M>(rec, nc.u1, nc.u2, nc.th, W.bA, W.lane);
+    Cell<double, M> nc;
+    if (normalise<double, M>(x.u1, x.u2, x.th, fs, W, nc)) store_record<double, M>(rec, nc.u1, nc.u2, nc.th, W.bA, W.lane);
     else if (W.lane == 0) atomicOr(err, 2);
     wsync();
   }
+}
+
+// FP32 smoothing blocks (FP32 sweeps, FP64 defect correction).
+// Working copies: g = g0 = fp32(f0) for every record entry; with `scale`,
+// the coefficients (not the basis parameters) are multiplied by *scale first.
+template <int M>
+__global__ void k_to32(int ncell, const double *__restrict__ src, float *__restrict__ g,
+                       float *__restrict__ g0, const double *__restrict__ scale) {
+  using g_ = G<M>;
+  const size_t tot = (size_t)ncell * g_::STRIDE;
+  const double sc = scale ? *scale : 1.0;
+  for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < tot;
+       x += (size_t)gridDim.x * blockDim.x) {
+    const int v = (int)(x % g_::STRIDE);
+    if (v >= g_::NR) continue;
+    const float y = (float)(v < 3 ? src[x] : src[x] * sc);
+    g[x] = y;
+    if (g0) g0[x] = y;
+  }
+}
+
+// f0 <- normalise(f0 + T(g0 -> f0)[T(g -> g0) g - g0] / scale) in FP64: the
+// FP32 increment of the block, formed exactly (g0 is the FP32 copy of f0),
+// divided by the block's defect scale and added to the FP64 state.  One
+// wavefront per cell.
+template <int M>
+__global__ __launch_bounds__(WAVE) void k_from32(LevelArgs A, double *__restrict__ f0,
+                                                 const float *__restrict__ g,
+                                                 const float *__restrict__ g0,
+                                                 const double *__restrict__ scale, int *err) {
+  using g_ = G<M>;
+  __shared__ double lds[3 * g_::CUBE + g_::MISC];
+  Wave<double, M> W;
+  W.init(lds, threadIdx.x);
+  const size_t off = (size_t)blockIdx.x * g_::STRIDE;
+  Cell<double, M> a, b, f;
+  a.u1 = g[off]; a.u2 = g[off + 1]; a.th = g[off + 2];
+  b.u1 = g0[off]; b.u2 = g0[off + 1]; b.th = g0[off + 2];
+#pragma unroll
+  for (int r = 0; r < g_::SL; ++r) {
+    a.f[r] = W.S.ok[r] ? (double)g[off + 3 + W.S.ci[r]] : 0.0;
+    b.f[r] = W.S.ok[r] ? (double)g0[off + 3 + W.S.ci[r]] : 0.0;
+  }
+  load_cell<double, M>(f0 + off, W.S, f);
+  double d[g_::SL];
+  put<double, M>(W.bX, W.S, a.f);
+  wsync();
+  bchange<double, M>(W.bX, W.bA, W.bB, b.u1 - a.u1, b.u2 - a.u2, b.th - a.th, W.S, d);
+  const double inv = 1.0 / *scale;
+#pragma unroll
+  for (int r = 0; r < g_::SL; ++r) d[r] = (d[r] - b.f[r]) * inv;
+  double t[g_::SL];
+  if (b.u1 == f.u1 && b.u2 == f.u2 && b.th == f.th) {
+#pragma unroll
+    for (int r = 0; r < g_::SL; ++r) t[r] = d[r];
+  } else {
+    put<double, M>(W.bX, W.S, d);
+    wsync();
+    bchange<double, M>(W.bX, W.bA, W.bB, f.u1 - b.u1, f.u2 - b.u2, f.th - b.th, W.S, t);
+  }
+  double fs[g_::SL];
+#pragma unroll
+  for (int r = 0; r < g_::SL; ++r) fs[r] = f.f[r] + t[r];
+  Cell<double, M> nc;
+  if (normalise<double, M>(f.u1, f.u2, f.th, fs, W, nc))
+    store_record<double, M>(f0 + off, nc.u1, nc.u2, nc.th, W.bA, W.lane);
+  else if (W.lane == 0)
+    atomicOr(err, 1);
 }
 
 template <int M>
@@ -1092,6 +1165,37 @@ __global__ __launch_bounds__(1024) void k_cell_sum(int ncell, const double *__re
     __syncthreads();
   }
   if (threadIdx.x == 0) *dst = part[0] * scale;
+}
+
+// Defect scale of an FP32 smoothing block.  `part` holds the per-cell
+// weighted squares of the FP64 defect d; n = ||d|| (eq. (28)).  The first
+// block on a level records dref = n; later blocks use
+// scale = max(1, tau dref / n), so that the FP32 unknowns of the block move by
+// about tau times the level's first correction however small d has become.
+__global__ __launch_bounds__(1024) void k_block_scale(int ncell, const double *__restrict__ part,
+                                                      double inv_area, double tau,
+                                                      double *__restrict__ dref,
+                                                      double *__restrict__ scale) {
+  __shared__ double sh[1024];
+  double s = 0.0;
+  for (int c = threadIdx.x; c < ncell; c += 1024) s += part[c];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double n = sqrt(sh[0] * inv_area);
+    double r = *dref;
+    if (!(r > 0.0)) {
+      r = n;
+      *dref = n;
+    }
+    double k = 1.0;
+    if (n > 0.0 && r > 0.0 && isfinite(n)) k = fmax(1.0, tau * r / n);
+    *scale = k;
+  }
 }
 
 // Mass correction of Sec. 4: scale every coefficient by mass0 / mass.
@@ -1134,9 +1238,9 @@ hipError_t launch_sweep_diag(int M, const LevelArgs &A, double *st, const double
   NRXX_DISPATCH_M(M, {
     constexpr int NW = TeamWidth<MM>::NW;
     if (A.order == 1)
-      hipLaunchKernelGGL((k_sweep_diag<MM, 1, NW>), dim3(ncell), dim3(NW * WAVE), 0, s, A, st, rhs, dir, t, a0, err);
+      hipLaunchKernelGGL((k_sweep_diag<double, MM, 1, NW>), dim3(ncell), dim3(NW * WAVE), 0, s, A, st, rhs, dir, t, a0, err);
     else
-      hipLaunchKernelGGL((k_sweep_diag<MM, 2, NW>), dim3(ncell), dim3(NW * WAVE), 0, s, A, st, rhs, dir, t, a0, err);
+      hipLaunchKernelGGL((k_sweep_diag<double, MM, 2, NW>), dim3(ncell), dim3(NW * WAVE), 0, s, A, st, rhs, dir, t, a0, err);
   });
   return hipGetLastError();
 }
@@ -1147,9 +1251,9 @@ hipError_t launch_sweep_persist(int M, const LevelArgs &A, double *st, const dou
   NRXX_DISPATCH_M(M, {
     constexpr int NW = TeamWidth<MM>::NW;
     if (A.order == 1)
-      hipLaunchKernelGGL((k_sweep_persist<MM, 1, NW>), dim3(A.nx), dim3(NW * WAVE), 0, s, A, st, rhs, nsweep, dirs, cnt, base, err, abort_flag, limit);
+      hipLaunchKernelGGL((k_sweep_persist<double, MM, 1, NW>), dim3(A.nx), dim3(NW * WAVE), 0, s, A, st, rhs, nsweep, dirs, cnt, base, err, abort_flag, limit);
     else
-      hipLaunchKernelGGL((k_sweep_persist<MM, 2, NW>), dim3(A.nx), dim3(NW * WAVE), 0, s, A, st, rhs, nsweep, dirs, cnt, base, err, abort_flag, limit);
+      hipLaunchKernelGGL((k_sweep_persist<double, MM, 2, NW>), dim3(A.nx), dim3(NW * WAVE), 0, s, A, st, rhs, nsweep, dirs, cnt, base, err, abort_flag, limit);
   });
   return hipGetLastError();
 }
@@ -1163,8 +1267,90 @@ int persist_max_columns(int M, int order) {
 #define NRXX_OCC(MM)                                                                              \
     case MM: {                                                                                    \
       constexpr int NW = TeamWidth<MM>::NW;                                                       \
-      e = order == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_persist<MM, 1, NW>, NW * WAVE, 0) \
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_persist<MM, 2, NW>, NW * WAVE, 0); \
+      e = order == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_persist<double, MM, 1, NW>, NW * WAVE, 0) \
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_persist<double, MM, 2, NW>, NW * WAVE, 0); \
+    } break;
+    NRXX_OCC(3) NRXX_OCC(4) NRXX_OCC(5) NRXX_OCC(6) NRXX_OCC(7) NRXX_OCC(8)
+#undef NRXX_OCC
+    default: return 0;
+  }
+  if (e != hipSuccess) return 0;
+  return per * ncu;
+}
+
+hipError_t launch_sweep_diag32(int M, const LevelArgs &A, float *st, const float *rhs, int dir,
+                               int t, int *err, hipStream_t s) {
+  const int a0 = t - (A.ny - 1) > 0 ? t - (A.ny - 1) : 0;
+  const int a1 = t < A.nx - 1 ? t : A.nx - 1;
+  const int ncell = a1 - a0 + 1;
+  if (ncell <= 0) return hipSuccess;
+  NRXX_DISPATCH_M(M, {
+    constexpr int NW = TeamWidth<MM>::NW;
+    if (A.order == 1)
+      hipLaunchKernelGGL((k_sweep_diag<float, MM, 1, NW>), dim3(ncell), dim3(NW * WAVE), 0, s, A, st, rhs, dir, t, a0, err);
+    else
+      hipLaunchKernelGGL((k_sweep_diag<float, MM, 2, NW>), dim3(ncell), dim3(NW * WAVE), 0, s, A, st, rhs, dir, t, a0, err);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_persist32(int M, const LevelArgs &A, float *st, const float *rhs,
+                                  int nsweep, unsigned dirs, int *cnt, int base, int *err,
+                                  int *abort_flag, unsigned long long limit, hipStream_t s) {
+  NRXX_DISPATCH_M(M, {
+    constexpr int NW = TeamWidth<MM>::NW;
+    if (A.order == 1)
+      hipLaunchKernelGGL((k_sweep_persist<float, MM, 1, NW>), dim3(A.nx), dim3(NW * WAVE), 0, s, A, st, rhs, nsweep, dirs, cnt, base, err, abort_flag, limit);
+    else
+      hipLaunchKernelGGL((k_sweep_persist<float, MM, 2, NW>), dim3(A.nx), dim3(NW * WAVE), 0, s, A, st, rhs, nsweep, dirs, cnt, base, err, abort_flag, limit);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_fas32(int M, const LevelArgs &A, const float *g0, const float *d32, float *out,
+                        hipStream_t s) {
+  const int ncell = A.nx * A.ny;
+  NRXX_DISPATCH_M(M, {
+    constexpr int NW = TeamWidth<MM>::NW;
+    if (A.order == 1)
+      hipLaunchKernelGGL((k_residual<float, MM, 1, NW, MODE_FAS>), dim3(ncell), dim3(NW * WAVE), 0, s, A, g0, (const float *)nullptr, d32, out, (float *)nullptr);
+    else
+      hipLaunchKernelGGL((k_residual<float, MM, 2, NW, MODE_FAS>), dim3(ncell), dim3(NW * WAVE), 0, s, A, g0, (const float *)nullptr, d32, out, (float *)nullptr);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_to32(int M, const LevelArgs &A, const double *src, float *g, float *g0,
+                       const double *scale, hipStream_t s) {
+  const int ncell = A.nx * A.ny;
+  NRXX_DISPATCH_M(M, {
+    const size_t tot = (size_t)ncell * G<MM>::STRIDE;
+    int blocks = (int)((tot + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL((k_to32<MM>), dim3(blocks), dim3(256), 0, s, ncell, src, g, g0, scale);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_from32(int M, const LevelArgs &A, double *f0, const float *g, const float *g0,
+                         const double *scale, int *err, hipStream_t s) {
+  NRXX_DISPATCH_M(M, {
+    hipLaunchKernelGGL((k_from32<MM>), dim3(A.nx * A.ny), dim3(WAVE), 0, s, A, f0, g, g0, scale, err);
+  });
+  return hipGetLastError();
+}
+
+int persist_max_columns32(int M, int order) {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (M) {
+#define NRXX_OCC(MM)                                                                              \
+    case MM: {                                                                                    \
+      constexpr int NW = TeamWidth<MM>::NW;                                                       \
+      e = order == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_persist<float, MM, 1, NW>, NW * WAVE, 0) \
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_persist<float, MM, 2, NW>, NW * WAVE, 0); \
     } break;
     NRXX_OCC(3) NRXX_OCC(4) NRXX_OCC(5) NRXX_OCC(6) NRXX_OCC(7) NRXX_OCC(8)
 #undef NRXX_OCC
@@ -1182,14 +1368,14 @@ hipError_t launch_residual(int M, const LevelArgs &A, const double *st, const do
     constexpr int NW = TeamWidth<MM>::NW;
     if (mode == 0) {
       if (A.order == 1)
-        hipLaunchKernelGGL((k_residual<MM, 1, NW, MODE_DEFECT>), dim3(ncell), dim3(NW * WAVE), 0, s, A, st, rhs, Radd, out, norm_part);
+        hipLaunchKernelGGL((k_residual<double, MM, 1, NW, MODE_DEFECT>), dim3(ncell), dim3(NW * WAVE), 0, s, A, st, rhs, Radd, out, norm_part);
       else
-        hipLaunchKernelGGL((k_residual<MM, 2, NW, MODE_DEFECT>), dim3(ncell), dim3(NW * WAVE), 0, s, A, st, rhs, Radd, out, norm_part);
+        hipLaunchKernelGGL((k_residual<double, MM, 2, NW, MODE_DEFECT>), dim3(ncell), dim3(NW * WAVE), 0, s, A, st, rhs, Radd, out, norm_part);
     } else {
       if (A.order == 1)
-        hipLaunchKernelGGL((k_residual<MM, 1, NW, MODE_FAS>), dim3(ncell), dim3(NW * WAVE), 0, s, A, st, rhs, Radd, out, norm_part);
+        hipLaunchKernelGGL((k_residual<double, MM, 1, NW, MODE_FAS>), dim3(ncell), dim3(NW * WAVE), 0, s, A, st, rhs, Radd, out, norm_part);
       else
-        hipLaunchKernelGGL((k_residual<MM, 2, NW, MODE_FAS>), dim3(ncell), dim3(NW * WAVE), 0, s, A, st, rhs, Radd, out, norm_part);
+        hipLaunchKernelGGL((k_residual<double, MM, 2, NW, MODE_FAS>), dim3(ncell), dim3(NW * WAVE), 0, s, A, st, rhs, Radd, out, norm_part);
     }
   });
   return hipGetLastError();
@@ -1229,6 +1415,13 @@ hipError_t launch_cell_sum(const LevelArgs &A, const double *src, int src_stride
                            double scale, double *dst, hipStream_t s) {
   hipLaunchKernelGGL(k_cell_sum, dim3(1), dim3(1024), 0, s, A.nx * A.ny, src, src_stride,
                      src_offset, scale, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_scale(const LevelArgs &A, const double *part, double tau, double *dref,
+                              double *scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_block_scale, dim3(1), dim3(1024), 0, s, A.nx * A.ny, part, A.inv_area, tau,
+                     dref, scale);
   return hipGetLastError();
 }
 

@@ -46,11 +46,14 @@ WORKLOADS = {
                                       order=2, limiter=1, wall_u=[0.0, 0.0, 0.5, 0.0], levels=4,
                                       tol=1e-10),
     # bottom-heated cavity: 256x256, Shakhov, Kn 0.05 or 0.2, M = 8, 2nd
-    # order, bottom wall theta 2, others 1, static, 5-level V-cycle
+    # order with the paper's central slopes (eq. (15)), bottom wall theta 2,
+    # others 1, static, 5-level V-cycle
     "heated256_shakhov_m8_kn005": dict(nx=256, ny=256, M=8, collision=1, Pr=2.0 / 3.0, Kn=0.05,
-                                       order=2, wall_theta=[2.0, 1.0, 1.0, 1.0], levels=5, tol=1e-8),
+                                       order=2, limiter=1, wall_theta=[2.0, 1.0, 1.0, 1.0],
+                                       levels=5, tol=1e-8),
     "heated256_shakhov_m8_kn02": dict(nx=256, ny=256, M=8, collision=1, Pr=2.0 / 3.0, Kn=0.2,
-                                      order=2, wall_theta=[2.0, 1.0, 1.0, 1.0], levels=5, tol=1e-8),
+                                      order=2, limiter=1, wall_theta=[2.0, 1.0, 1.0, 1.0],
+                                      levels=5, tol=1e-8),
     # the paper's Table-1 setup in dimensionless form: Shakhov, Kn 0.1, M = 5,
     # 1st order, U_W = 50 m/s at 273 K (0.2097 in sqrt(R T0) units), 8x8
     # coarsest grid

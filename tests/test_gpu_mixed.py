@@ -1,0 +1,110 @@
+"""GPU: FP32 smoothing blocks with FP64 defect correction (precision 1).
+
+The sweeps run in FP32 on a scaled correction problem while the defect,
+restriction, coarse right-hand side, correction and mass fix stay FP64.  The
+fixed point is the FP64 discrete steady state, so converged fields are
+compared with the FP64 oracle and the FP64 GPU path; each test prints the
+error it measured.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import context, require_gpu, state_err
+from paper_2206_13164_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def mirror_err(st, M):
+    """Distance of a cavity state from its x-mirror image (cell i -> nx-1-i,
+    u1 -> -u1, f_alpha -> (-1)^alpha_1 f_alpha), in the units of state_err."""
+    al = I.alpha_list(M)
+    m = st[:, ::-1, :].copy()
+    m[..., 0] *= -1.0
+    m[..., 3:] *= np.where(al[:, 0] % 2 == 1, -1.0, 1.0)
+    return state_err(m, st, M)
+
+
+def test_mixed_solve_matches_fp64_oracle_config1(orc):
+    # 32x32 BGK M = 3 lid cavity: the mixed solve reaches relative residual
+    # 1e-10 and its field is the FP64 oracle's converged field
+    require_gpu()
+    s = I.spec("lid32_bgk_m3")
+    P = orc.problem(s)
+    orc.set_threads(8)
+    try:
+        want = I.maxwellian_state(s)
+        rc, cyc64, _ = orc.solve(P, want, 1e-10, 80)
+    finally:
+        orc.set_threads(1)
+    assert rc == 0
+    ctx = context(dict(s, precision=1))
+    d = ctx.empty(0)
+    ctx.init_maxwellian(d)
+    rc, cyc, hist = ctx.solve(d, 1e-10, 80)
+    assert rc == 0, hist
+    err = state_err(ctx.to_host(d, want.shape[-1]), want, s["M"])
+    print(f"mixed: {cyc} cycles (FP64 oracle {cyc64}), field error vs oracle {err:.2e}")
+    assert cyc <= cyc64 + 3
+    assert err < 1e-8
+
+
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_mixed_heated_cavity_reduced(schedule):
+    # config-3 physics (bottom-heated, Shakhov, Kn 0.05, M = 8, 2nd order) on
+    # 32x32 with 3 levels: residual 1e-8 reached, x-mirror symmetric, and the
+    # same field as the FP64 path
+    require_gpu()
+    s = I.spec("heated256_shakhov_m8_kn005", nx=32, ny=32, levels=3, schedule=schedule)
+    ref_ctx = context(s)
+    ref = ref_ctx.empty(0)
+    ref_ctx.init_maxwellian(ref)
+    rc, c64, _ = ref_ctx.solve(ref, 1e-11, 150)
+    assert rc == 0
+    ctx = context(dict(s, precision=1))
+    d = ctx.empty(0)
+    ctx.init_maxwellian(d)
+    rc, cyc, hist = ctx.solve(d, 1e-8, 150)
+    assert rc == 0, hist
+    nrec = I.nalpha(8) + 3
+    got, want = ctx.to_host(d, nrec), ref_ctx.to_host(ref, nrec)
+    err, mir = state_err(got, want, 8), mirror_err(got, 8)
+    print(f"mixed: {cyc} cycles to 1e-8 (FP64: {c64} to 1e-11), error vs FP64 {err:.2e}, "
+          f"mirror {mir:.2e} (FP64 mirror {mirror_err(want, 8):.2e})")
+    assert err < 1e-6 and mir < 1e-6
+
+
+def test_mixed_schedules_agree_bitwise():
+    # FP32 persistent and per-diagonal sweeps give identical blocks
+    require_gpu()
+    for M, coll, order in ((3, 0, 1), (5, 1, 2), (8, 1, 2)):
+        s = I.spec(None, M=M, collision=coll, Pr=2.0 / 3.0 if coll else 1.0, order=order,
+                   nx=16, ny=12, levels=2, Kn=0.15, wall_u=[0.1, -0.15, 0.35, 0.05],
+                   wall_theta=[1.6, 1.0, 0.9, 1.2], precision=1)
+        ca, cb = context(dict(s, schedule=1)), context(dict(s, schedule=2))
+        assert cb.level_schedule(0) == 2
+        st = I.random_state(s, seed=23, amp=0.06)
+        a, b = ca.to_device(st), cb.to_device(st)
+        ca.sweep(a, nsteps=2)
+        cb.sweep(b, nsteps=2)
+        assert bool((a == b).all()), M
+
+
+def test_mixed_first_block_close_to_fp64_sweep():
+    # the first block on a level has scale 1: one FP32 step of the FP64
+    # defect equation from a random state lands within FP32 rounding of
+    # the FP64 step
+    require_gpu()
+    s = I.spec("lid128_shakhov_m5", nx=32, ny=32, levels=2)
+    st = I.random_state(s, seed=5, amp=0.05)
+    c64, c32 = context(s), context(dict(s, precision=1))
+    a, b = c64.to_device(st), c32.to_device(st)
+    c64.sweep(a)
+    c32.sweep(b)
+    n = st.shape[-1]
+    ga, gb = c64.to_host(a, n), c32.to_host(b, n)
+    err = state_err(gb, ga, 5)
+    step = state_err(ga, st, 5)
+    print(f"one step: FP64 change {step:.2e}, FP32-block difference {err:.2e}")
+    assert err < 1e-5 * max(step, 1.0)
+    assert step > 1e-3
