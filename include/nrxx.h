@@ -196,6 +196,75 @@ int nrxx_solve(nrxx_ctx *ctx, double *state, double tol, int max_cycles, double 
 int nrxx_sweep_stats(nrxx_ctx *ctx, double *ms_out, double *cell_updates_out,
                      double *launches_out, int reset);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent problems solved together on one device.
+ *
+ * A batch holds n problem descriptions that share `levels`, s1, s2, s3 and
+ * gamma (precision must be 0); grids, M, order, Kn, walls, collision model
+ * and Pr may differ.  Problems with the same (M, order) form a group; each
+ * group runs its V-cycles on a stream of its own (created by the batch, at
+ * the default priority), with persistent work-queue sweep kernels whose
+ * units are (problem, grid column, sweep direction): every cell is updated in
+ * the serial order of Alg. 1, so each problem's result is bitwise the one
+ * nrxx_sweep / nrxx_fas_vcycle give for it alone.  Each problem stops
+ * independently when its residual norm (eq. (28)) falls to tol times its
+ * initial norm; converged problems are masked off on the device.
+ *
+ * `states` arguments are host arrays of n device pointers, problem i's
+ * finest-level record array (layout of the single-problem calls); the caller
+ * owns them.  Calls are enqueued on the batch streams and synchronise with
+ * the stream given to nrxx_batch_create before returning.
+ * ------------------------------------------------------------------------- */
+typedef struct nrxx_batch nrxx_batch;
+
+/* Execution choice of one group (see nrxx_batch_autotune). */
+typedef struct {
+  int32_t M, order;      /* the group (read only) */
+  int32_t problems;      /* problems in the group (read only) */
+  int32_t team_width;    /* wavefronts per cell team: 8 (M <= 5 only), 4, 2 or 1 */
+  int32_t grid;          /* persistent sweep workgroups (>= 1) */
+  int32_t unit_order;    /* 0: units ordered by column position, then problem;
+                            1: by problem (largest first), then column position */
+  double block_ms;       /* last autotune: time of one s1-step block on level 0 */
+} nrxx_batch_tuning;
+
+/* Validates every problem as nrxx_create does, plus the shared fields; builds
+ * the groups, their level tables and coarse levels.  Initial tuning: the
+ * default team width, every resident workgroup, unit_order 0. */
+int nrxx_batch_create(const nrxx_problem *problems, int32_t n, void *hip_stream,
+                      nrxx_batch **out);
+int nrxx_batch_destroy(nrxx_batch *b);
+const char *nrxx_batch_last_error(const nrxx_batch *b);
+int nrxx_batch_groups(const nrxx_batch *b);
+int nrxx_batch_get_tuning(const nrxx_batch *b, int group, nrxx_batch_tuning *out);
+/* Sets team_width, grid and unit_order of a group (NRXX_EINVAL if invalid). */
+int nrxx_batch_set_tuning(nrxx_batch *b, int group, const nrxx_batch_tuning *t);
+/* Times every candidate (team width x grid {all resident, half} x unit order)
+ * on one s1-step smoothing block of the finest level of `states`, keeps the
+ * fastest per group, and restores `states` bit for bit. */
+int nrxx_batch_autotune(nrxx_batch *b, double *const *states);
+/* Global Maxwellian in every problem. */
+int nrxx_batch_init_maxwellian(nrxx_batch *b, double *const *states, double rho, double u1,
+                               double u2, double theta);
+/* Residual norm of eq. (28) of every problem (norms_out: n doubles). */
+int nrxx_batch_residual_norms(nrxx_batch *b, double *const *states, double *norms_out);
+/* `nsteps` fast-sweeping steps (all four directions) on every problem's
+ * finest level, r = 0 (as nrxx_sweep with dir_mask 15). */
+int nrxx_batch_sweep(nrxx_batch *b, double *const *states, int nsteps);
+/* One NMG iteration (Alg. 2 + mass fix) on every problem, as
+ * nrxx_fas_vcycle; norms_out (n doubles, may be NULL) gets the new norms. */
+int nrxx_batch_vcycle(nrxx_batch *b, double *const *states, double *norms_out);
+/* Solve every problem to ||R|| <= tol * ||R(initial)|| or max_cycles
+ * V-cycles.  use_graph != 0 replays each group's cycle from a HIP graph
+ * captured on first use (re-captured after a tuning change).  Outputs (n
+ * each, may be NULL): cycles taken, final and initial norms.  NRXX_OK when
+ * every problem converged, NRXX_EMAXIT otherwise (states valid). */
+int nrxx_batch_solve(nrxx_batch *b, double *const *states, double tol, int32_t max_cycles,
+                     int32_t use_graph, int32_t *cycles_out, double *norms_out, double *ref_out);
+/* Device time (ms) of the batch's V-cycles and the cell updates their sweeps
+ * made since creation or the last reset. */
+int nrxx_batch_stats(nrxx_batch *b, double *ms_out, double *cell_updates_out, int reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnrxx.so")
-SOURCES = ["nrxx_kernels.hip", "nrxx_api.cpp"]
+SOURCES = ["nrxx_kernels.hip", "nrxx_batch.hip", "nrxx_api.cpp", "nrxx_batch_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -20,7 +20,7 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
+    objs, procs = [], []
     for src in SOURCES:
         obj = os.path.join(CSRC, src + ".o")
         cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
@@ -28,8 +28,11 @@ def build(verbose: bool = False) -> str:
             cmd.insert(1, "-xhip")
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        procs.append((cmd, subprocess.Popen(cmd)))
         objs.append(obj)
+    for cmd, p in procs:  # translation units compile in parallel
+        if p.wait() != 0:
+            raise subprocess.CalledProcessError(p.returncode, cmd)
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

@@ -11,7 +11,7 @@
 #include <vector>
 
 #include "../../include/nrxx.h"
-#include "nrxx_internal.hpp"
+#include "nrxx_host.hpp"
 
 using namespace nrxx;
 
@@ -318,6 +318,77 @@ int mass_fix_impl(nrxx_ctx *c, double *st) {
 
 }  // namespace
 
+namespace nrxx {
+
+namespace {
+bool bad(std::string &msg, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  msg = buf;
+  return false;
+}
+}  // namespace
+
+bool validate_problem(const nrxx_problem &P, std::string &msg) {
+  if (P.M < MMIN || P.M > MMAX) return bad(msg, "M = %d outside [%d, %d]", P.M, MMIN, MMAX);
+  if (P.levels < 1 || P.levels > 16) return bad(msg, "levels = %d", P.levels);
+  if (P.nx < 1 || P.ny < 1) return bad(msg, "grid %d x %d", P.nx, P.ny);
+  const int f = 1 << (P.levels - 1);
+  if (P.nx % f || P.ny % f) return bad(msg, "grid %d x %d not divisible by 2^(levels-1) = %d", P.nx, P.ny, f);
+  if (P.nx / f < 2 || P.ny / f < 2) return bad(msg, "coarsest grid below 2 x 2");
+  if (P.collision != 0 && P.collision != 1) return bad(msg, "collision = %d", P.collision);
+  if (P.order != 1 && P.order != 2) return bad(msg, "order = %d", P.order);
+  if (P.limiter != 0 && P.limiter != 1) return bad(msg, "limiter = %d", P.limiter);
+  if (!(P.lx > 0) || !(P.ly > 0) || !(P.Kn > 0) || !(P.cfl > 0) || !(P.beta > 0))
+    return bad(msg, "lx, ly, Kn, cfl and beta must be positive");
+  for (int w = 0; w < 4; ++w)
+    if (!(P.wall_theta[w] > 0)) return bad(msg, "wall_theta[%d] <= 0", w);
+  if (P.s1 < 0 || P.s2 < 0 || P.s3 < 0 || P.gamma < 1 || P.gamma > 2)
+    return bad(msg, "bad smoothing steps or gamma");
+  if (P.precision != 0 && P.precision != 1)
+    return bad(msg, "precision = %d not supported", P.precision);
+  if (P.schedule < 0 || P.schedule > 2) return bad(msg, "schedule = %d", P.schedule);
+  if ((long long)P.nx * P.ny > (1LL << 26)) return bad(msg, "grid too large");
+
+  return true;
+}
+
+LevelArgs make_level(const nrxx_problem &P, int k) {
+  double jm[MMAX + 1] = {0};
+  wall_entering_constants(P.M, jm);
+  LevelArgs A{};
+  A.nx = P.nx >> k;
+  A.ny = P.ny >> k;
+  A.stride = record_stride(P.M);
+  A.collision = P.collision;
+  A.order = P.order;
+  A.limiter = P.limiter;
+  A.dx = P.lx / A.nx;
+  A.dy = P.ly / A.ny;
+  A.idx = 1.0 / A.dx;
+  A.idy = 1.0 / A.dy;
+  A.ds = A.dx * A.dy;
+  A.inv_area = 1.0 / (P.lx * P.ly);
+  A.Kn = P.Kn;
+  A.Pr = P.Pr;
+  A.omega = P.omega;
+  A.beta = P.beta;
+  A.cfl = P.cfl;
+  A.nu_cap = P.nu_dt_cap;
+  A.C = largest_hermite_root(P.M + 1);
+  for (int w = 0; w < 4; ++w) {
+    A.wall_u[w] = P.wall_u[w];
+    A.wall_th[w] = P.wall_theta[w];
+  }
+  for (int q = 0; q <= MMAX; ++q) A.jminus[q] = jm[q];
+  return A;
+}
+
+}  // namespace nrxx
+
 extern "C" {
 
 int32_t nrxx_record_stride(int32_t M) { return (M >= MMIN && M <= MMAX) ? record_stride(M) : -1; }
@@ -327,61 +398,18 @@ int nrxx_create(const nrxx_problem *p, void *hip_stream, nrxx_ctx **out) {
   *out = nullptr;
   if (!p) return fail(nullptr, NRXX_EINVAL, "problem is NULL");
   const nrxx_problem &P = *p;
-  if (P.M < MMIN || P.M > MMAX) return fail(nullptr, NRXX_EINVAL, "M = %d outside [%d, %d]", P.M, MMIN, MMAX);
-  if (P.levels < 1 || P.levels > 16) return fail(nullptr, NRXX_EINVAL, "levels = %d", P.levels);
-  if (P.nx < 1 || P.ny < 1) return fail(nullptr, NRXX_EINVAL, "grid %d x %d", P.nx, P.ny);
-  const int f = 1 << (P.levels - 1);
-  if (P.nx % f || P.ny % f) return fail(nullptr, NRXX_EINVAL, "grid %d x %d not divisible by 2^(levels-1) = %d", P.nx, P.ny, f);
-  if (P.nx / f < 2 || P.ny / f < 2) return fail(nullptr, NRXX_EINVAL, "coarsest grid below 2 x 2");
-  if (P.collision != 0 && P.collision != 1) return fail(nullptr, NRXX_EINVAL, "collision = %d", P.collision);
-  if (P.order != 1 && P.order != 2) return fail(nullptr, NRXX_EINVAL, "order = %d", P.order);
-  if (P.limiter != 0 && P.limiter != 1) return fail(nullptr, NRXX_EINVAL, "limiter = %d", P.limiter);
-  if (!(P.lx > 0) || !(P.ly > 0) || !(P.Kn > 0) || !(P.cfl > 0) || !(P.beta > 0))
-    return fail(nullptr, NRXX_EINVAL, "lx, ly, Kn, cfl and beta must be positive");
-  for (int w = 0; w < 4; ++w)
-    if (!(P.wall_theta[w] > 0)) return fail(nullptr, NRXX_EINVAL, "wall_theta[%d] <= 0", w);
-  if (P.s1 < 0 || P.s2 < 0 || P.s3 < 0 || P.gamma < 1 || P.gamma > 2)
-    return fail(nullptr, NRXX_EINVAL, "bad smoothing steps or gamma");
-  if (P.precision != 0 && P.precision != 1)
-    return fail(nullptr, NRXX_EINVAL, "precision = %d not supported", P.precision);
-  if (P.schedule < 0 || P.schedule > 2) return fail(nullptr, NRXX_EINVAL, "schedule = %d", P.schedule);
-  if ((long long)P.nx * P.ny > (1LL << 26)) return fail(nullptr, NRXX_EINVAL, "grid too large");
-
+  {
+    std::string msg;
+    if (!validate_problem(P, msg)) return fail(nullptr, NRXX_EINVAL, "%s", msg.c_str());
+  }
   nrxx_ctx *c = new nrxx_ctx();
   c->P = P;
   c->stream = (hipStream_t)hip_stream;
   c->M = P.M;
   c->stride = record_stride(P.M);
   c->L = P.levels;
-  double jm[MMAX + 1] = {0};
-  wall_entering_constants(P.M, jm);
-  const double C = largest_hermite_root(P.M + 1);
   for (int k = 0; k < c->L; ++k) {
-    LevelArgs A{};
-    A.nx = P.nx >> k;
-    A.ny = P.ny >> k;
-    A.stride = c->stride;
-    A.collision = P.collision;
-    A.order = P.order;
-    A.limiter = P.limiter;
-    A.dx = P.lx / A.nx;
-    A.dy = P.ly / A.ny;
-    A.idx = 1.0 / A.dx;
-    A.idy = 1.0 / A.dy;
-    A.ds = A.dx * A.dy;
-    A.inv_area = 1.0 / (P.lx * P.ly);
-    A.Kn = P.Kn;
-    A.Pr = P.Pr;
-    A.omega = P.omega;
-    A.beta = P.beta;
-    A.cfl = P.cfl;
-    A.nu_cap = P.nu_dt_cap;
-    A.C = C;
-    for (int w = 0; w < 4; ++w) {
-      A.wall_u[w] = P.wall_u[w];
-      A.wall_th[w] = P.wall_theta[w];
-    }
-    for (int q = 0; q <= MMAX; ++q) A.jminus[q] = jm[q];
+    LevelArgs A = make_level(P, k);
     c->lv.push_back(A);
   }
   c->Rbar.assign(c->L, nullptr);

@@ -74,4 +74,43 @@ hipError_t launch_cell_sum(const LevelArgs &A, const double *src, int src_stride
 hipError_t launch_mass_scale(int M, const LevelArgs &A, double *st, const double *mass,
                              double mass0, hipStream_t s);
 
+
+// ---- batched instances (nrxx_batch.hip) ------------------------------------
+// One instance at one level of a group (device table entry).  Level 0 `st`
+// is the caller's state; coarse `st` is f~_H.  cell0 = first cell of the
+// instance in the group's cell numbering of the level (entries sorted by it).
+struct BLevel {
+  LevelArgs A;
+  double *st, *rhs, *Rbar, *fbar, *RH;
+  int *cnt;  // nx progress counters of the sweep kernel
+  int cell0, ncell, inst;
+  double mass0;
+};
+bool batch_width_ok(int M, int nw);
+int batch_default_width(int M);
+// Persistent work-queue sweeps: units[U] = (slot << 16 | column position),
+// nsweep sweeps (2 direction bits each in dirs); *queue and every instance's
+// counters must be zero at launch.
+hipError_t launch_bsweep(int M, int order, int nw, int grid, const BLevel *tab, const int *units,
+                         int U, int nsweep, unsigned dirs, int *queue, const int *active, int *err,
+                         int *abort_flag, unsigned long long limit, hipStream_t s);
+int bsweep_resident(int M, int order, int nw);
+// role 0: Rbar = rhs - R(st); 1: rhs = R(fbar) + RH; 2: partial = weighted squares
+hipError_t launch_bresidual(int M, int order, int ncell, const BLevel *tab, int nslot,
+                            const int *active, int role, double *partial, hipStream_t s);
+hipError_t launch_brestrict(int M, int ncell_coarse, const BLevel *tabF, const BLevel *tabC,
+                            int nslot, const int *active, int *err, hipStream_t s);
+hipError_t launch_bcopy(int M, int ncell, const BLevel *tab, int nslot, const int *active,
+                        hipStream_t s);
+hipError_t launch_bcorrect(int M, int ncell_coarse, const BLevel *tabF, const BLevel *tabC,
+                           int nslot, const int *active, int *err, hipStream_t s);
+// what 0: out[inst] = norm from partial; 1: out[inst] = mass of st
+hipError_t launch_bsum(const BLevel *tab, int nslot, int stride, const int *active,
+                       const double *partial, int what, double *out, hipStream_t s);
+hipError_t launch_bmass_scale(int M, int ncell, const BLevel *tab, int nslot, const int *active,
+                              const double *mass, hipStream_t s);
+hipError_t launch_bstatus(const BLevel *tab, int nslot, const double *norms, const double *ref,
+                          const double *tol, int *active, int *cycles, int *err, hipStream_t s);
+hipError_t launch_bfill(int *p, int n, int v, hipStream_t s);
+
 }  // namespace nrxx

@@ -38,6 +38,13 @@ class Problem(ctypes.Structure):
     ]
 
 
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("M", c_int), ("order", c_int), ("problems", c_int), ("team_width", c_int),
+                ("grid", c_int), ("unit_order", c_int), ("block_ms", c_double)]
+
+
+_PP = ctypes.POINTER(c_void_p)
+
 EXPORTS = {
     "nrxx_record_stride": (c_int, [c_int]),
     "nrxx_create": (c_int, [ctypes.POINTER(Problem), c_void_p, ctypes.POINTER(c_void_p)]),
@@ -57,6 +64,19 @@ EXPORTS = {
                            c_void_p]),
     "nrxx_sweep_stats": (c_int, [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double),
                                  ctypes.POINTER(c_double), c_int]),
+    "nrxx_batch_create": (c_int, [ctypes.POINTER(Problem), c_int, c_void_p, ctypes.POINTER(c_void_p)]),
+    "nrxx_batch_destroy": (c_int, [c_void_p]),
+    "nrxx_batch_last_error": (ctypes.c_char_p, [c_void_p]),
+    "nrxx_batch_groups": (c_int, [c_void_p]),
+    "nrxx_batch_get_tuning": (c_int, [c_void_p, c_int, ctypes.POINTER(BatchTuning)]),
+    "nrxx_batch_set_tuning": (c_int, [c_void_p, c_int, ctypes.POINTER(BatchTuning)]),
+    "nrxx_batch_autotune": (c_int, [c_void_p, _PP]),
+    "nrxx_batch_init_maxwellian": (c_int, [c_void_p, _PP, c_double, c_double, c_double, c_double]),
+    "nrxx_batch_residual_norms": (c_int, [c_void_p, _PP, c_void_p]),
+    "nrxx_batch_sweep": (c_int, [c_void_p, _PP, c_int]),
+    "nrxx_batch_vcycle": (c_int, [c_void_p, _PP, c_void_p]),
+    "nrxx_batch_solve": (c_int, [c_void_p, _PP, c_double, c_int, c_int, c_void_p, c_void_p, c_void_p]),
+    "nrxx_batch_stats": (c_int, [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double), c_int]),
 }
 
 _lib = None
@@ -217,3 +237,102 @@ class Context:
         self._chk(load().nrxx_sweep_stats(self.h, ctypes.byref(ms), ctypes.byref(cells),
                                           ctypes.byref(launches), int(reset)))
         return ms.value, cells.value, launches.value
+
+
+class Batch:
+    """Owns an nrxx_batch: many problems (specs) solved together.  States are
+    lists of float64 CUDA tensors, one per problem, shaped
+    (ny, nx, record_stride(M)) for that problem's finest level."""
+
+    def __init__(self, specs, stream=None):
+        import torch
+        self.torch = torch
+        L = load()
+        self.specs = [dict(x) for x in specs]
+        self.n = len(self.specs)
+        arr = (Problem * self.n)(*[problem(x) for x in self.specs])
+        self._arr = arr
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = c_void_p()
+        rc = L.nrxx_batch_create(arr, self.n, c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if rc != NRXX_OK:
+            raise NrxxError(rc, L.nrxx_batch_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().nrxx_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc, allow=()):
+        if rc != NRXX_OK and rc not in allow:
+            raise NrxxError(rc, load().nrxx_batch_last_error(self.h).decode())
+        return rc
+
+    def _ptrs(self, states):
+        if len(states) != self.n:
+            raise ValueError("need one state per problem")
+        return (c_void_p * self.n)(*[t.data_ptr() for t in states])
+
+    def empty_states(self):
+        out = []
+        for x in self.specs:
+            st = record_stride(int(x["M"]))
+            out.append(self.torch.zeros((x["ny"], x["nx"], st), dtype=self.torch.float64,
+                                        device="cuda"))
+        return out
+
+    def groups(self):
+        return load().nrxx_batch_groups(self.h)
+
+    def tuning(self, group):
+        t = BatchTuning()
+        self._chk(load().nrxx_batch_get_tuning(self.h, group, ctypes.byref(t)))
+        return {k: getattr(t, k) for k, _ in BatchTuning._fields_}
+
+    def set_tuning(self, group, team_width, grid, unit_order):
+        t = BatchTuning()
+        t.team_width, t.grid, t.unit_order = team_width, grid, unit_order
+        self._chk(load().nrxx_batch_set_tuning(self.h, group, ctypes.byref(t)))
+
+    def autotune(self, states):
+        self._chk(load().nrxx_batch_autotune(self.h, self._ptrs(states)))
+
+    def init_maxwellian(self, states, rho=1.0, u=(0.0, 0.0), theta=1.0):
+        self._chk(load().nrxx_batch_init_maxwellian(self.h, self._ptrs(states), rho, u[0], u[1], theta))
+
+    def residual_norms(self, states):
+        out = np.zeros(self.n)
+        self._chk(load().nrxx_batch_residual_norms(self.h, self._ptrs(states),
+                                                   out.ctypes.data_as(c_void_p)))
+        return out
+
+    def sweep(self, states, nsteps=1):
+        self._chk(load().nrxx_batch_sweep(self.h, self._ptrs(states), nsteps))
+
+    def vcycle(self, states):
+        out = np.zeros(self.n)
+        self._chk(load().nrxx_batch_vcycle(self.h, self._ptrs(states), out.ctypes.data_as(c_void_p)))
+        return out
+
+    def solve(self, states, tol, max_cycles, use_graph=True):
+        cyc = np.zeros(self.n, dtype=np.int32)
+        nrm, ref = np.zeros(self.n), np.zeros(self.n)
+        rc = load().nrxx_batch_solve(self.h, self._ptrs(states), tol, max_cycles, int(use_graph),
+                                     cyc.ctypes.data_as(c_void_p), nrm.ctypes.data_as(c_void_p),
+                                     ref.ctypes.data_as(c_void_p))
+        self._chk(rc, allow=(NRXX_EMAXIT,))
+        return rc, cyc, nrm, ref
+
+    def stats(self, reset=False):
+        ms, cells = c_double(), c_double()
+        self._chk(load().nrxx_batch_stats(self.h, ctypes.byref(ms), ctypes.byref(cells), int(reset)))
+        return ms.value, cells.value

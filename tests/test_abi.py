@@ -59,3 +59,28 @@ def test_null_arguments():
     assert L.nrxx_destroy(None) == N.NRXX_OK
     assert L.nrxx_residual(None, 0, None, None, None, None) == N.NRXX_EINVAL
     assert L.nrxx_solve(None, None, 1e-8, 1, 0.0, None, None) == N.NRXX_EINVAL
+
+
+@pytest.mark.parametrize("bad", [
+    [dict(levels=2), dict(levels=3, nx=64, ny=64)],   # levels must be shared
+    [dict(), dict(s1=3)],                              # smoothing steps must be shared
+    [dict(), dict(precision=1)],                       # batches are FP64
+    [dict(), dict(M=9)],                               # invalid member
+])
+def test_batch_create_rejects_invalid_sets_before_touching_the_gpu(bad):
+    L = N.load()
+    specs = [I.spec("lid32_bgk_m3", **kw) for kw in bad]
+    arr = (N.Problem * len(specs))(*[N.problem(x) for x in specs])
+    h = ctypes.c_void_p(123)
+    rc = L.nrxx_batch_create(arr, len(specs), None, ctypes.byref(h))
+    assert rc == N.NRXX_EINVAL
+    assert h.value is None
+    assert len(L.nrxx_batch_last_error(None)) > 0
+    assert L.nrxx_batch_create(arr, 0, None, ctypes.byref(h)) == N.NRXX_EINVAL
+
+
+def test_batch_null_arguments():
+    L = N.load()
+    assert L.nrxx_batch_destroy(None) == N.NRXX_OK
+    assert L.nrxx_batch_groups(None) == N.NRXX_EINVAL
+    assert L.nrxx_batch_solve(None, None, 1e-8, 1, 0, None, None, None) == N.NRXX_EINVAL

@@ -1,0 +1,148 @@
+"""GPU: batches of heterogeneous problems (work-queue persistent sweeps,
+batched V-cycle kernels, per-problem convergence masks, graph replay,
+autotuner).  Every problem of a batch must give bitwise the result of the
+single-problem library, which is itself parity-tested against the oracle."""
+import numpy as np
+import pytest
+
+from gpu_common import context, require_gpu
+from paper_2206_13164_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def mixed_specs(levels=2):
+    base = dict(levels=levels, wall_u=[0.1, -0.15, 0.35, 0.05], wall_theta=[1.6, 1.0, 0.9, 1.2])
+    return [
+        I.spec(None, M=3, collision=0, Pr=1.0, order=1, nx=16, ny=12, Kn=0.3, **base),
+        I.spec(None, M=5, collision=1, Pr=2.0 / 3.0, order=2, limiter=0, nx=24, ny=16, Kn=0.1, **base),
+        I.spec(None, M=5, collision=0, Pr=1.0, order=2, limiter=1, nx=16, ny=20, Kn=0.05, **base),
+        I.spec(None, M=8, collision=1, Pr=2.0 / 3.0, order=2, limiter=1, nx=12, ny=12, Kn=0.2, **base),
+        I.spec(None, M=3, collision=1, Pr=2.0 / 3.0, order=1, nx=8, ny=24, Kn=1.0, **base),
+    ]
+
+
+def random_states(batch, specs, seed):
+    out = []
+    for k, s in enumerate(specs):
+        st = I.random_state(s, seed=seed + k, amp=0.06)
+        t = batch.empty_states()[k]
+        t[..., : st.shape[-1]] = batch.torch.from_numpy(st).to("cuda")
+        out.append(t)
+    return out
+
+
+def single_results(specs, states, fn):
+    res = []
+    for s, st in zip(specs, states):
+        ctx = context(s)
+        d = st.clone()
+        fn(ctx, d)
+        res.append(d)
+    return res
+
+
+def test_batch_sweep_bitwise_equals_single_problem_sweeps():
+    require_gpu()
+    from paper_2206_13164_amd import nrxx as N
+    specs = mixed_specs()
+    b = N.Batch(specs)
+    assert b.groups() == 3  # (M, order) = (3, 1), (5, 2), (8, 2)
+    st0 = random_states(b, specs, 31)
+    want = single_results(specs, st0, lambda c, d: c.sweep(d, nsteps=2))
+    # every tuning candidate, including a grid far smaller than the columns
+    for g in range(b.groups()):
+        t = b.tuning(g)
+        assert t["team_width"] in (1, 2, 4, 8) and t["grid"] >= 1
+    full = [b.tuning(g)["grid"] for g in range(b.groups())]
+    for width in (8, 4, 2, 1):
+        for grid in (None, 3):
+            for order in (0, 1):
+                for g in range(b.groups()):
+                    w = 4 if (width == 8 and b.tuning(g)["M"] > 5) else width
+                    b.set_tuning(g, w, grid or full[g], order)
+                st = [x.clone() for x in st0]
+                b.sweep(st, nsteps=2)
+                for k in range(len(specs)):
+                    assert bool((st[k] == want[k]).all()), (k, width_choice, grid, order)
+
+
+def test_batch_vcycle_bitwise_equals_single_problem_vcycles():
+    require_gpu()
+    from paper_2206_13164_amd import nrxx as N
+    specs = mixed_specs(levels=2)
+    b = N.Batch(specs)
+    st = [x.clone() for x in random_states(b, specs, 41)]
+    want_norms = []
+
+    def one(ctx, d):
+        want_norms.append(ctx.fas_vcycle(d))
+
+    want = single_results(specs, st, one)
+    got_norms = b.vcycle(st)
+    for k in range(len(specs)):
+        assert bool((st[k] == want[k]).all()), k
+    assert np.array_equal(got_norms, np.array(want_norms))
+
+
+def test_batch_solve_masks_graph_replays_and_cycle_counts():
+    require_gpu()
+    from paper_2206_13164_amd import nrxx as N
+    specs = [
+        I.spec("lid32_bgk_m3", nx=16, ny=16),
+        I.spec("lid32_bgk_m3", Kn=0.02),
+        I.spec("paper_table1_32", levels=2),
+        I.spec("lid128_shakhov_m5_central", nx=32, ny=32, levels=2),
+    ]
+    tol = 1e-8
+    b = N.Batch(specs)
+    # graph replays, one cycle per call with eager host work in between, equal
+    # the eager path after every replay
+    sg, se = b.empty_states(), b.empty_states()
+    b.init_maxwellian(sg)
+    b.init_maxwellian(se)
+    for rep in range(3):
+        rc, cyc, nrm_g, _ = b.solve(sg, 0.0, 1, use_graph=True)
+        _ = float(nrm_g.sum())  # host work between replays
+        rc2, cyc2, nrm_e, _ = b.solve(se, 0.0, 1, use_graph=False)
+        for k in range(len(specs)):
+            assert bool((sg[k] == se[k]).all()), (rep, k)
+        assert np.array_equal(nrm_g, nrm_e)
+    # full solve: every problem stops on its own and matches the single
+    # library's solve bit for bit
+    st = b.empty_states()
+    b.init_maxwellian(st)
+    rc, cyc, nrm, ref = b.solve(st, tol, 80, use_graph=True)
+    assert rc == N.NRXX_OK
+    assert np.all(nrm <= tol * ref)
+    assert len(set(cyc.tolist())) > 1  # the masks did stop problems at different cycles
+    for k, s in enumerate(specs):
+        ctx = context(s)
+        d = ctx.empty(0)
+        ctx.init_maxwellian(d)
+        rc1, c1, h1 = ctx.solve(d, tol, 80)
+        assert rc1 == N.NRXX_OK and c1 == cyc[k], (k, c1, cyc[k])
+        assert bool((d == st[k]).all()), k
+        assert h1[-1] == nrm[k]
+    ms, cells = b.stats(reset=True)
+    assert ms > 0 and cells > 0
+
+
+def test_batch_autotune_restores_states_and_keeps_results():
+    require_gpu()
+    from paper_2206_13164_amd import nrxx as N
+    specs = mixed_specs()
+    b = N.Batch(specs)
+    st = random_states(b, specs, 51)
+    before = [x.clone() for x in st]
+    b.autotune(st)
+    for k in range(len(specs)):
+        assert bool((st[k] == before[k]).all()), k
+    for g in range(b.groups()):
+        t = b.tuning(g)
+        assert t["block_ms"] > 0 and t["grid"] >= 1 and t["unit_order"] in (0, 1)
+        print("group", g, t)
+    want = single_results(specs, before, lambda c, d: c.sweep(d, nsteps=1))
+    b.sweep(st, nsteps=1)
+    for k in range(len(specs)):
+        assert bool((st[k] == want[k]).all()), k
