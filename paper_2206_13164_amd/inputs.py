@@ -154,3 +154,69 @@ def random_rhs(s: dict, level: int, seed: int, amp: float = 0.02):
     coef[..., odd] = 0.0
     st[..., 3:] = coef[..., :N]
     return st
+
+
+# ---------------------------------------------------------------------------
+# Cavity parameter draws and the warm-start network's inputs
+# ---------------------------------------------------------------------------
+
+# Layer widths of the warm-start network: 8 inputs, three hidden layers of
+# 256, 9 outputs (rho, u1, u2, theta, sigma11, sigma12, sigma22, q1, q2).
+MLP_LAYERS = (8, 256, 256, 256, 9)
+FIELD_NAMES = ("rho", "u1", "u2", "theta", "s11", "s12", "s22", "q1", "q2")
+FEATURE_NAMES = ("log10Kn", "lid", "thS", "thE", "thN", "thW", "x", "y")
+
+# seeds of the draws: training set, held-out set, network initialisation
+SEED_TRAIN, SEED_TEST, SEED_INIT = 220613165, 220613166, 220613167
+SEED_BATCH = 220613164
+
+
+def cavity_draws(n: int, seed: int, sides=(64, 96, 128, 192, 256), Ms=(3, 5, 8), levels=4,
+                 kn_range=(0.01, 1.0), lid_range=(0.1, 0.5), **overrides) -> list[dict]:
+    """Lid-driven cavities with randomly drawn parameters, in the draw order
+    (side, Kn, lid speed, M, collision model) per cavity: side uniform over
+    `sides`, Kn log-uniform, lid speed uniform, M uniform over `Ms`, BGK or
+    Shakhov (Pr 2/3) with probability 1/2; second order (central slopes),
+    walls at theta = 1."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        side = int(rng.choice(sides))
+        kn = float(np.exp(rng.uniform(np.log(kn_range[0]), np.log(kn_range[1]))))
+        lid = float(rng.uniform(*lid_range))
+        M = int(rng.choice(Ms))
+        coll = int(rng.integers(0, 2))
+        d = dict(nx=side, ny=side, M=M, collision=coll, Pr=2.0 / 3.0 if coll else 1.0, Kn=kn,
+                 order=2, limiter=1, wall_u=[0.0, 0.0, lid, 0.0], levels=levels, tol=1e-8)
+        d.update(overrides)
+        out.append(spec(None, **d))
+    return out
+
+
+def mlp_features(s: dict, nx: int, ny: int) -> np.ndarray:
+    """Network inputs of every cell centre of an nx x ny grid over the
+    cavity of spec s: (log10 Kn, lid speed, wall theta S/E/N/W, x, y), rows in
+    row-major cell order, float32."""
+    x = (np.arange(nx) + 0.5) / nx * s["lx"]
+    y = (np.arange(ny) + 0.5) / ny * s["ly"]
+    X, Y = np.meshgrid(x, y)
+    F = np.zeros((ny * nx, 8), dtype=np.float32)
+    F[:, 0] = math.log10(s["Kn"])
+    F[:, 1] = s["wall_u"][2]
+    F[:, 2:6] = np.asarray(s["wall_theta"], dtype=np.float32)
+    F[:, 6] = X.ravel()
+    F[:, 7] = Y.ravel()
+    return F
+
+
+def mlp_init(seed: int = SEED_INIT, layers=MLP_LAYERS) -> list[tuple[np.ndarray, np.ndarray]]:
+    """Seeded initial parameters: per layer W (out x in) and b (out), uniform
+    in +-1/sqrt(fan_in), float64."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(len(layers) - 1):
+        a = 1.0 / math.sqrt(layers[k])
+        W = rng.uniform(-a, a, size=(layers[k + 1], layers[k]))
+        b = rng.uniform(-a, a, size=layers[k + 1])
+        out.append((W, b))
+    return out
