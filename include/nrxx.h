@@ -265,6 +265,59 @@ int nrxx_batch_solve(nrxx_batch *b, double *const *states, double tol, int32_t m
  * made since creation or the last reset. */
 int nrxx_batch_stats(nrxx_batch *b, double *ms_out, double *cell_updates_out, int reset);
 
+/* ---------------------------------------------------------------------------
+ * Warm start from macroscopic fields, and the warm-start network.
+ * ------------------------------------------------------------------------- */
+
+/* Fill the finest-level `state` from macroscopic fields given on an
+ * fnx x fny grid that divides the finest grid (each cell takes the fields of
+ * the field cell it lies in).  fields: device, fny x fnx x 9 floats,
+ * (rho, u1, u2, theta, sigma11, sigma12, sigma22, q1, q2) per cell; the
+ * record is the Grad-type closure in the basis [u, theta]: f_0 = rho,
+ * f_{e_i+e_j} = sigma_ij / (1 + delta_ij) with sigma33 = -(sigma11 +
+ * sigma22), f_{3e_i} = f_{e_i+2e_d} = q_i / 5 (d != i), all else 0, which
+ * reproduces rho, u, theta, sigma and q (eq. (10) relations).  Synchronises;
+ * NRXX_ENONPHYS if some rho or theta is not positive (the state is then
+ * unusable and the caller should start from a Maxwellian). */
+int nrxx_init_fields(nrxx_ctx *ctx, double *state, const float *fields, int32_t fnx, int32_t fny);
+
+/* The nine fields above for every cell of `state` on `level` (device output,
+ * ny x nx x 9 floats): rho = f_0, (u, theta) of the basis,
+ * sigma_ij = (1 + delta_ij) f_{e_i+e_j}, q_i = 2 f_{3e_i} + sum_d f_{2e_d+e_i}. */
+int nrxx_state_fields(nrxx_ctx *ctx, int level, const double *state, float *fields);
+
+/* A fully connected network y = L_n(s(... s(L_1(x)))) with affine layers L_k
+ * (W_k: widths[k+1] x widths[k], b_k), SiLU s(z) = z / (1 + e^-z), inputs
+ * standardised ((x - in_mean) / in_std) and outputs de-standardised
+ * (y * out_std + out_mean).  Products use BF16 operands with FP32
+ * accumulation on the matrix cores; weights keep FP32 masters.  Training
+ * minimises the mean over rows and outputs of the squared error in
+ * standardised output units with Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+ * X, Y, T are device row-major float arrays (rows x widths[0], rows x
+ * widths[n]); parameters on the host are, per layer, W row-major then b. */
+typedef struct nrxx_mlp nrxx_mlp;
+int nrxx_mlp_create(const int32_t *widths, int32_t nlayers, int32_t max_rows, void *hip_stream,
+                    nrxx_mlp **out);
+int nrxx_mlp_destroy(nrxx_mlp *m);
+const char *nrxx_mlp_last_error(const nrxx_mlp *m);
+int64_t nrxx_mlp_param_count(const nrxx_mlp *m);
+/* Loads parameters (host floats) and resets the optimiser state. */
+int nrxx_mlp_set_params(nrxx_mlp *m, const float *params);
+int nrxx_mlp_get_params(const nrxx_mlp *m, float *params);
+/* Host arrays of widths[0] and widths[n] floats; standard deviations > 0. */
+int nrxx_mlp_set_scaling(nrxx_mlp *m, const float *in_mean, const float *in_std,
+                         const float *out_mean, const float *out_std);
+int nrxx_mlp_forward(nrxx_mlp *m, const float *X, int32_t rows, float *Y);
+/* Gradients of the loss on (X, T) with respect to every parameter, written
+ * to host `grads` in the parameter layout; loss_out (may be NULL) gets the
+ * loss.  Synchronises. */
+int nrxx_mlp_gradients(nrxx_mlp *m, const float *X, const float *T, int32_t rows, float *grads,
+                       double *loss_out);
+/* One Adam step of learning rate lr on the batch (X, T); loss_out (may be
+ * NULL; synchronises if not) gets the loss before the step. */
+int nrxx_mlp_train_step(nrxx_mlp *m, const float *X, const float *T, int32_t rows, float lr,
+                        double *loss_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -657,4 +657,21 @@ int nrxx_sweep_stats(nrxx_ctx *c, double *ms_out, double *cells_out, double *lau
   return NRXX_OK;
 }
 
+int nrxx_init_fields(nrxx_ctx *c, double *state, const float *fields, int32_t fnx, int32_t fny) {
+  if (!c) return NRXX_EINVAL;
+  const LevelArgs &A = c->lv[0];
+  if (!state || !fields || fnx < 1 || fny < 1 || A.nx % fnx || A.ny % fny)
+    return fail(c, NRXX_EINVAL, "NULL buffer or field grid %d x %d does not divide %d x %d", fnx, fny,
+                A.nx, A.ny);
+  CHK(launch_init_fields(c->M, A, state, fields, fnx, fny, c->derr, c->stream));
+  return check_device(c);
+}
+
+int nrxx_state_fields(nrxx_ctx *c, int level, const double *state, float *fields) {
+  if (!c) return NRXX_EINVAL;
+  if (!level_ok(c, level) || !state || !fields) return fail(c, NRXX_EINVAL, "bad level or NULL buffer");
+  CHK(launch_state_fields(c->M, c->lv[level], state, fields, c->stream));
+  return NRXX_OK;
+}
+
 }  // extern "C"

@@ -75,6 +75,14 @@ hipError_t launch_mass_scale(int M, const LevelArgs &A, double *st, const double
                              double mass0, hipStream_t s);
 
 
+// Records of a level from macroscopic fields on a coarser fnx x fny grid
+// (injection; bit 0 of *err for rho or theta not positive), and the nine
+// fields of every cell of a level.
+hipError_t launch_init_fields(int M, const LevelArgs &A, double *st, const float *fields, int fnx,
+                              int fny, int *err, hipStream_t s);
+hipError_t launch_state_fields(int M, const LevelArgs &A, const double *st, float *fields,
+                               hipStream_t s);
+
 // ---- batched instances (nrxx_batch.hip) ------------------------------------
 // One instance at one level of a group (device table entry).  Level 0 `st`
 // is the caller's state; coarse `st` is f~_H.  cell0 = first cell of the

@@ -191,6 +191,75 @@ __global__ __launch_bounds__(WAVE) void k_from32(LevelArgs A, double *__restrict
     atomicOr(err, 1);
 }
 
+// Graded-order positions of the coefficients a Grad-type closure sets:
+// 0 (000), 1 (200), 2 (020), 3 (002), 4 (110), 5 (300), 6 (120), 7 (102),
+// 8 (210), 9 (030), 10 (012).
+struct FieldIdx {
+  int k[11];
+};
+
+// Cell records from macroscopic fields (rho, u1, u2, theta, sigma11,
+// sigma12, sigma22, q1, q2) given on a coarser fnx x fny grid (injection):
+// basis [u, theta], f_0 = rho, f_{e_i+e_j} = sigma_ij / (1 + delta_ij) with a
+// traceless stress, f_{3e_i} = f_{e_i+2e_d} = q_i / 5, everything else 0.
+// A cell whose rho or theta is not positive and finite sets bit 0 of *err.
+template <int M>
+__global__ void k_init_fields(int nx, int ny, double *__restrict__ st, const float *__restrict__ F,
+                              int fnx, int fny, FieldIdx ix, int *err) {
+  using g = G<M>;
+  const size_t tot = (size_t)nx * ny * g::STRIDE;
+  const int rx = nx / fnx, ry = ny / fny;
+  for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < tot;
+       x += (size_t)gridDim.x * blockDim.x) {
+    const int v = (int)(x % g::STRIDE);
+    if (v >= g::NR) continue;
+    const int cell = (int)(x / g::STRIDE);
+    const int i = cell % nx, j = cell / nx;
+    const float *f = F + ((size_t)(j / ry) * fnx + i / rx) * 9;
+    double val = 0.0;
+    if (v < 3) {
+      val = f[1 + v];
+      if (v == 2 && !(val > 0.0 && isfinite(val))) atomicOr(err, 1);
+    } else {
+      const int a = v - 3;
+      const double s11 = f[4], s12 = f[5], s22 = f[6], q1 = f[7], q2 = f[8];
+      if (a == ix.k[0]) {
+        val = f[0];
+        if (!(val > 0.0 && isfinite(val))) atomicOr(err, 1);
+      } else if (a == ix.k[1]) val = s11 / 2.0;
+      else if (a == ix.k[2]) val = s22 / 2.0;
+      else if (a == ix.k[3]) val = -(s11 + s22) / 2.0;
+      else if (a == ix.k[4]) val = s12;
+      else if (a == ix.k[5] || a == ix.k[6] || a == ix.k[7]) val = q1 / 5.0;
+      else if (a == ix.k[8] || a == ix.k[9] || a == ix.k[10]) val = q2 / 5.0;
+    }
+    st[x] = val;
+  }
+}
+
+// Macroscopic fields of every cell (eq. (10) relations): rho = f_0, u,
+// theta from the basis, sigma_ij = (1 + delta_ij) f_{e_i+e_j},
+// q_i = 2 f_{3e_i} + sum_d f_{2e_d+e_i}; nine floats per cell.
+template <int M>
+__global__ void k_state_fields(int ncell, const double *__restrict__ st, FieldIdx ix,
+                               float *__restrict__ F) {
+  using g = G<M>;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += gridDim.x * blockDim.x) {
+    const double *r = st + (size_t)c * g::STRIDE;
+    const double *f = r + 3;
+    float *o = F + (size_t)c * 9;
+    o[0] = (float)f[ix.k[0]];
+    o[1] = (float)r[0];
+    o[2] = (float)r[1];
+    o[3] = (float)r[2];
+    o[4] = (float)(2.0 * f[ix.k[1]]);
+    o[5] = (float)f[ix.k[4]];
+    o[6] = (float)(2.0 * f[ix.k[2]]);
+    o[7] = (float)(3.0 * f[ix.k[5]] + f[ix.k[6]] + f[ix.k[7]]);
+    o[8] = (float)(3.0 * f[ix.k[9]] + f[ix.k[8]] + f[ix.k[10]]);
+  }
+}
+
 template <int M>
 __global__ void k_init_maxwellian(int ncell, double *__restrict__ st, double rho, double u1,
                                   double u2, double th) {
@@ -476,6 +545,49 @@ hipError_t launch_mass_scale(int M, const LevelArgs &A, double *st, const double
     int blocks = (int)((tot + 255) / 256);
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL((k_mass_scale<MM>), dim3(blocks), dim3(256), 0, s, ncell, st, mass, mass0);
+  });
+  return hipGetLastError();
+}
+
+
+namespace {
+// position of alpha in the graded order (|alpha| ascending; alpha_1, then
+// alpha_2 descending within a degree)
+int graded_index(int a1, int a2, int a3) {
+  const int n = a1 + a2 + a3;
+  int pos = n * (n + 1) * (n + 2) / 6;
+  for (int b1 = n; b1 > a1; --b1) pos += n - b1 + 1;
+  return pos + (n - a1 - a2);
+}
+FieldIdx field_idx() {
+  static const int A[11][3] = {{0, 0, 0}, {2, 0, 0}, {0, 2, 0}, {0, 0, 2}, {1, 1, 0}, {3, 0, 0},
+                               {1, 2, 0}, {1, 0, 2}, {2, 1, 0}, {0, 3, 0}, {0, 1, 2}};
+  FieldIdx ix;
+  for (int q = 0; q < 11; ++q) ix.k[q] = graded_index(A[q][0], A[q][1], A[q][2]);
+  return ix;
+}
+}  // namespace
+
+hipError_t launch_init_fields(int M, const LevelArgs &A, double *st, const float *fields, int fnx,
+                              int fny, int *err, hipStream_t s) {
+  const FieldIdx ix = field_idx();
+  NRXX_DISPATCH_M(M, {
+    const size_t tot = (size_t)A.nx * A.ny * G<MM>::STRIDE;
+    int blocks = (int)((tot + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL((k_init_fields<MM>), dim3(blocks), dim3(256), 0, s, A.nx, A.ny, st, fields, fnx, fny, ix, err);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_state_fields(int M, const LevelArgs &A, const double *st, float *fields,
+                               hipStream_t s) {
+  const FieldIdx ix = field_idx();
+  const int ncell = A.nx * A.ny;
+  NRXX_DISPATCH_M(M, {
+    int blocks = (ncell + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL((k_state_fields<MM>), dim3(blocks), dim3(256), 0, s, ncell, st, ix, fields);
   });
   return hipGetLastError();
 }

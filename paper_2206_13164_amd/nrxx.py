@@ -77,6 +77,20 @@ EXPORTS = {
     "nrxx_batch_vcycle": (c_int, [c_void_p, _PP, c_void_p]),
     "nrxx_batch_solve": (c_int, [c_void_p, _PP, c_double, c_int, c_int, c_void_p, c_void_p, c_void_p]),
     "nrxx_batch_stats": (c_int, [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double), c_int]),
+    "nrxx_init_fields": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int]),
+    "nrxx_state_fields": (c_int, [c_void_p, c_int, c_void_p, c_void_p]),
+    "nrxx_mlp_create": (c_int, [c_void_p, c_int, c_int, c_void_p, ctypes.POINTER(c_void_p)]),
+    "nrxx_mlp_destroy": (c_int, [c_void_p]),
+    "nrxx_mlp_last_error": (ctypes.c_char_p, [c_void_p]),
+    "nrxx_mlp_param_count": (ctypes.c_int64, [c_void_p]),
+    "nrxx_mlp_set_params": (c_int, [c_void_p, c_void_p]),
+    "nrxx_mlp_get_params": (c_int, [c_void_p, c_void_p]),
+    "nrxx_mlp_set_scaling": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "nrxx_mlp_forward": (c_int, [c_void_p, c_void_p, c_int, c_void_p]),
+    "nrxx_mlp_gradients": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p,
+                                   ctypes.POINTER(c_double)]),
+    "nrxx_mlp_train_step": (c_int, [c_void_p, c_void_p, c_void_p, c_int, ctypes.c_float,
+                                    ctypes.POINTER(c_double)]),
 }
 
 _lib = None
@@ -231,6 +245,17 @@ class Context:
         self._chk(rc, allow=(NRXX_EMAXIT,))
         return rc, cyc.value, hist[: cyc.value + 1]
 
+    def init_fields(self, state, fields):
+        """fields: float32 CUDA tensor (fny, fnx, 9) on a grid dividing the finest."""
+        fny, fnx, _ = fields.shape
+        self._chk(load().nrxx_init_fields(self.h, _ptr(state), _ptr(fields), fnx, fny))
+
+    def state_fields(self, state, level=0):
+        nx, ny = self.level_shape(level)
+        out = self.torch.zeros((ny, nx, 9), dtype=self.torch.float32, device="cuda")
+        self._chk(load().nrxx_state_fields(self.h, level, _ptr(state), _ptr(out)))
+        return out
+
     def sweep_stats(self, reset=False):
         """(device ms in sweep kernels, cell updates, sweep kernel launches)."""
         ms, cells, launches = c_double(), c_double(), c_double()
@@ -336,3 +361,91 @@ class Batch:
         ms, cells = c_double(), c_double()
         self._chk(load().nrxx_batch_stats(self.h, ctypes.byref(ms), ctypes.byref(cells), int(reset)))
         return ms.value, cells.value
+
+
+class Mlp:
+    """Owns an nrxx_mlp (the warm-start network).  Parameters travel as one
+    flat float32 host array (per layer: W row-major, then b)."""
+
+    def __init__(self, widths, max_rows, stream=None):
+        import torch
+        self.torch = torch
+        L = load()
+        self.widths = [int(w) for w in widths]
+        w = (c_int * len(self.widths))(*self.widths)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = c_void_p()
+        rc = L.nrxx_mlp_create(w, len(self.widths) - 1, int(max_rows), c_void_p(stream.cuda_stream),
+                               ctypes.byref(h))
+        if rc != NRXX_OK:
+            raise NrxxError(rc, L.nrxx_mlp_last_error(None).decode())
+        self.h = h
+        self.n_params = int(L.nrxx_mlp_param_count(h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().nrxx_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        if rc != NRXX_OK:
+            raise NrxxError(rc, load().nrxx_mlp_last_error(self.h).decode())
+
+    @staticmethod
+    def flatten(params):
+        return np.concatenate([np.concatenate([np.asarray(W, np.float32).ravel(),
+                                               np.asarray(b, np.float32).ravel()])
+                               for W, b in params]).astype(np.float32)
+
+    def unflatten(self, flat):
+        out, off = [], 0
+        for k in range(len(self.widths) - 1):
+            o, i = self.widths[k + 1], self.widths[k]
+            W = flat[off:off + o * i].reshape(o, i)
+            off += o * i
+            out.append((W, flat[off:off + o]))
+            off += o
+        return out
+
+    def set_params(self, params):
+        flat = np.ascontiguousarray(self.flatten(params) if isinstance(params, list) else params,
+                                    dtype=np.float32)
+        assert flat.size == self.n_params
+        self._chk(load().nrxx_mlp_set_params(self.h, flat.ctypes.data_as(c_void_p)))
+
+    def get_params(self):
+        flat = np.zeros(self.n_params, dtype=np.float32)
+        self._chk(load().nrxx_mlp_get_params(self.h, flat.ctypes.data_as(c_void_p)))
+        return flat
+
+    def set_scaling(self, in_mean, in_std, out_mean, out_std):
+        a = [np.ascontiguousarray(x, dtype=np.float32) for x in (in_mean, in_std, out_mean, out_std)]
+        self._a = a
+        self._chk(load().nrxx_mlp_set_scaling(self.h, *[x.ctypes.data_as(c_void_p) for x in a]))
+
+    def forward(self, X):
+        rows = X.shape[0]
+        Y = self.torch.empty((rows, self.widths[-1]), dtype=self.torch.float32, device="cuda")
+        self._chk(load().nrxx_mlp_forward(self.h, _ptr(X), rows, _ptr(Y)))
+        return Y
+
+    def gradients(self, X, T):
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = c_double()
+        self._chk(load().nrxx_mlp_gradients(self.h, _ptr(X), _ptr(T), X.shape[0],
+                                            g.ctypes.data_as(c_void_p), ctypes.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, X, T, lr, want_loss=False):
+        loss = c_double()
+        self._chk(load().nrxx_mlp_train_step(self.h, _ptr(X), _ptr(T), X.shape[0], float(lr),
+                                             ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
