@@ -117,6 +117,56 @@ def time_variant(spec, tol, max_cycles, ref, NA):
             "time_to_residual_s": wall, "cycles": cyc, "final_rel_residual": hist[-1] / ref}
 
 
+def learned_leg(max_cycles):
+    """Config-5 comparison on a held-out cavity (256x256, M = 5, 6 levels,
+    tol 1e-8 relative to the Maxwellian start's residual): plain FP64 from
+    the Maxwellian vs the learned start in FP64 and with FP32 smoothing
+    blocks; times include the network's inference and the start check."""
+    from paper_2206_13164_amd import inputs as I
+    from paper_2206_13164_amd import warmstart as W
+    if not os.path.exists(W.DEFAULT_WEIGHTS):
+        return {"skipped": "no trained network"}
+    ws = W.WarmStart()
+    s = I.cavity_draws(1, I.SEED_TEST, sides=(256,), Ms=(5,), levels=6)[0]
+    r = W.compare(s, ws, tol=1e-8, max_cycles=max_cycles)
+    base = r["maxwellian_p0"]["seconds"]
+    return {"cavity": {"grid": "256x256", "M": 5, "Kn": s["Kn"], "lid": s["wall_u"][2],
+                       "collision": "Shakhov" if s["collision"] else "BGK", "levels": 6,
+                       "tol": 1e-8},
+            **r,
+            "speedup_learned_fp64": base / r["learned_p0"]["seconds"],
+            "speedup_learned_mixed": base / r["learned_p1"]["seconds"],
+            "network": {k: v for k, v in ws.meta.items() if k != "loss"}}
+
+
+def batch_leg(n=16, cycles=6):
+    """Batched throughput: n drawn cavities (sides 64/96/128, M 3/5/8,
+    BGK/Shakhov, Kn log-uniform in [0.01, 1]) in one batch after autotuning,
+    `cycles` graph-replayed V-cycles."""
+    import torch
+    from paper_2206_13164_amd import inputs as I
+    from paper_2206_13164_amd import nrxx as N
+    specs = I.cavity_draws(n, I.SEED_BATCH, sides=(64, 96, 128))
+    b = N.Batch(specs)
+    st = b.empty_states()
+    b.init_maxwellian(st)
+    b.autotune(st)
+    b.solve(st, 0.0, 1)  # capture the graphs, load the code objects
+    b.init_maxwellian(st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, cyc, nrm, ref = b.solve(st, 0.0, cycles, use_graph=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    upd = sum(int(c) * cycle_accounting(x)["cells"] * math.comb(x["M"] + 3, 3) for c, x in zip(cyc, specs))
+    tun = [b.tuning(g) for g in range(b.groups())]
+    b.close()
+    return {"problems": n, "cycles": cycles, "seconds": wall,
+            "cell_moment_updates_per_s": upd / wall,
+            "tuning": [{k: t[k] for k in ("M", "order", "problems", "team_width", "grid", "unit_order")}
+                       for t in tun]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +174,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="lid128_shakhov_m5_central")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned warm-start comparison (256x256 held-out cavity)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-throughput leg")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the FP32-sweep (precision 1) solve of the same workload")
     ap.add_argument("--max-cycles", type=int, default=200)
@@ -239,6 +292,10 @@ def main():
     if not args.no_mixed:
         out["mixed"] = time_variant(dict(spec, precision=1), tol, args.max_cycles, ref, NA)
         out["mixed"]["speedup_vs_plain"] = (wall / args.steps) / out["mixed"]["time_to_residual_s"]
+    if not args.no_batch:
+        out["batch"] = batch_leg()
+    if not args.no_learned:
+        out["learned"] = learned_leg(args.max_cycles)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, 20.0)
     print(json.dumps(out), flush=True)
