@@ -20,7 +20,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "smoother cell-moment updates/s + time-to-residual 1e-8, plain vs mixed/learned"
-KERNEL_SRC = os.path.join(ROOT, "paper_2206_13164_amd", "csrc", "nrxx_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2206_13164_amd", "csrc", f)
+               for f in ("nrxx_device.hpp", "nrxx_kernels.hip")]
 PROFILES = os.path.join(ROOT, "profiles")
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
@@ -56,6 +57,15 @@ def cycle_accounting(spec):
     return tot
 
 
+def kernel_source_hash() -> str:
+    """sha256 over the sources of the single-problem kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
 def profiled_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` on `workload` from the committed
     FETCH_SIZE / WRITE_SIZE summary, or None when the summary is missing or
@@ -69,7 +79,7 @@ def profiled_traffic(kernel: str, workload: str):
         if ":" in line and line.startswith("- "):
             k, v = line[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    src = kernel_source_hash()
     if vals.get("kernel_source_sha256") != src or "traffic_bytes_per_launch" not in vals:
         return None
     return float(vals["traffic_bytes_per_launch"])

@@ -35,6 +35,17 @@ __device__ __forceinline__ int find_slot(const BLevel *__restrict__ tab, int nsl
   return lo;
 }
 
+// Copies a problem's level constants into LDS once per workgroup: the cell
+// team reads them many times, and reading them through the table in global
+// memory puts a dependent scalar load on every use.
+__device__ __forceinline__ void stage_args(const LevelArgs &src, LevelArgs &dst) {
+  constexpr int n = (int)(sizeof(LevelArgs) / sizeof(uint32_t));
+  const uint32_t *s = reinterpret_cast<const uint32_t *>(&src);
+  uint32_t *d = reinterpret_cast<uint32_t *>(&dst);
+  for (int x = threadIdx.x; x < n; x += blockDim.x) d[x] = s[x];
+  __syncthreads();
+}
+
 template <int M, int ORDER, int NW>
 __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__ tab,
                                                       const int *__restrict__ units, int U,
@@ -44,6 +55,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__
   using L = Lay<M, NW>;
   __shared__ double lds[L::TOTAL];
   __shared__ int su;
+  __shared__ LevelArgs sA;
   double *sc = lds + L::S;
   const int total = nsweep * U;
   for (;;) {
@@ -60,7 +72,10 @@ __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__
     const int slot = e >> 16, p = e & 0xffff;
     const BLevel &B = tab[slot];
     if (!active[B.inst]) continue;
-    const int nx = B.A.nx, ny = B.A.ny;
+    stage_args(B.A, sA);
+    double *const st = B.st;
+    const double *const rhs = B.rhs;
+    const int nx = sA.nx, ny = sA.ny;
     int *cnt = B.cnt;
     const int dir = (dirs >> (2 * s)) & 3;
     const bool irev = dir == 1 || dir == 2, jrev = dir == 2 || dir == 3;
@@ -91,8 +106,8 @@ __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__
         if (threadIdx.x == 0) atomicOr(err, 4);
         return;  // uniform across the team
       }
-      cell_team<double, M, ORDER, NW, MODE_SWEEP>(B.A, lds, B.st, B.rhs, nullptr, nullptr,
-                                                  nullptr, i, j, err);
+      cell_team<double, M, ORDER, NW, MODE_SWEEP>(sA, lds, st, rhs, nullptr, nullptr, nullptr, i,
+                                                  j, err);
       if (threadIdx.x == 0)
         __hip_atomic_store(cnt + i, s * ny + b + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       __syncthreads();
@@ -107,19 +122,21 @@ __global__ __launch_bounds__(NW * WAVE) void k_bresidual(const BLevel *__restric
                                                          const int *__restrict__ active, int role,
                                                          double *partial) {
   __shared__ double lds[Lay<M, NW>::TOTAL];
+  __shared__ LevelArgs sA;
   const int slot = find_slot(tab, nslot, blockIdx.x);
   const BLevel &B = tab[slot];
   if (!active[B.inst]) return;
+  stage_args(B.A, sA);
   const int cell = blockIdx.x - B.cell0;
-  const int i = cell % B.A.nx, j = cell / B.A.nx;
+  const int i = cell % sA.nx, j = cell / sA.nx;
   if (role == 1)
-    cell_team<double, M, ORDER, NW, MODE>(B.A, lds, B.fbar, nullptr, B.RH, B.rhs, nullptr, i, j,
+    cell_team<double, M, ORDER, NW, MODE>(sA, lds, B.fbar, nullptr, B.RH, B.rhs, nullptr, i, j,
                                           nullptr);
   else if (role == 0)
-    cell_team<double, M, ORDER, NW, MODE>(B.A, lds, B.st, B.rhs, nullptr, B.Rbar, nullptr, i, j,
+    cell_team<double, M, ORDER, NW, MODE>(sA, lds, B.st, B.rhs, nullptr, B.Rbar, nullptr, i, j,
                                           nullptr);
   else
-    cell_team<double, M, ORDER, NW, MODE>(B.A, lds, B.st, B.rhs, nullptr, nullptr,
+    cell_team<double, M, ORDER, NW, MODE>(sA, lds, B.st, B.rhs, nullptr, nullptr,
                                           partial + B.cell0, i, j, nullptr);
 }
 
