@@ -199,9 +199,10 @@ int nrxx_sweep_stats(nrxx_ctx *ctx, double *ms_out, double *cell_updates_out,
 /* ---------------------------------------------------------------------------
  * Batches: many independent problems solved together on one device.
  *
- * A batch holds n problem descriptions that share `levels`, s1, s2, s3 and
- * gamma (precision must be 0); grids, M, order, Kn, walls, collision model
- * and Pr may differ.  Problems with the same (M, order) form a group; each
+ * A batch holds n problem descriptions that share s1, s2, s3 and gamma
+ * (precision must be 0); grids, level counts, M, order, Kn, walls,
+ * collision model and Pr may differ (a problem takes its s3 coarsest steps on
+ * its own coarsest level while the others recurse further).  Problems with the same (M, order) form a group; each
  * group runs its V-cycles on a stream of its own (created by the batch, at
  * the default priority), with persistent work-queue sweep kernels whose
  * units are (problem, grid column, sweep direction): every cell is updated in

@@ -115,7 +115,8 @@ __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__
   }
 }
 
-// role 0: Rbar = rhs - R(st); role 1: rhs = R(fbar) + RH (eq. (22));
+// role 0: Rbar = rhs - R(st) (problems that continue to a coarser level);
+// role 1: rhs = R(fbar) + RH (eq. (22));
 // role 2: partial[cell0 + cell] = weighted |rhs - R(st)|^2 ds (eq. (28)).
 template <int M, int ORDER, int NW, int MODE>
 __global__ __launch_bounds__(NW * WAVE) void k_bresidual(const BLevel *__restrict__ tab, int nslot,
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_bresidual(const BLevel *__restric
   __shared__ LevelArgs sA;
   const int slot = find_slot(tab, nslot, blockIdx.x);
   const BLevel &B = tab[slot];
-  if (!active[B.inst]) return;
+  if (!active[B.inst] || (role == 0 && !B.cont)) return;
   stage_args(B.A, sA);
   const int cell = blockIdx.x - B.cell0;
   const int i = cell % sA.nx, j = cell / sA.nx;

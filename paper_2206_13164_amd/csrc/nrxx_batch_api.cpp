@@ -28,8 +28,10 @@ struct nrxx_batch {
     std::vector<int> ncell;                 // cells of the group per level
     std::vector<int *> cnt;                 // [queue | counters of every slot]
     std::vector<int> cntsize;
-    std::vector<int *> units[2];            // per unit order, per level
-    std::vector<int> U;                     // units per sweep per level
+    // unit lists per unit order, per level, for the problems that continue
+    // to a coarser level (c = 0) and for those whose coarsest level it is (1)
+    std::vector<int *> units[2][2];
+    std::vector<int> U[2];                  // units per sweep per level
     double *partial = nullptr;              // level-0 per-cell scalars
     std::vector<void *> owned;
     int nw = 0, grid = 0, major = 0;
@@ -80,29 +82,33 @@ int bhip(nrxx_batch *b, hipError_t e, const char *what) {
 
 using Group = nrxx_batch::Group;
 
-int steps_at(const nrxx_batch *b, int k) { return k == b->L - 1 ? b->s3 : b->s1 + b->s2; }
-
 double cycle_cells(const nrxx_batch *b, int inst) {
+  const nrxx_problem &P = b->P[inst];
   double c = 0.0;
-  for (int k = 0; k < b->L; ++k)
-    c += 4.0 * steps_at(b, k) * (double)(b->P[inst].nx >> k) * (b->P[inst].ny >> k);
+  for (int k = 0; k < P.levels; ++k) {
+    const int steps = k == P.levels - 1 ? b->s3 : b->s1 + b->s2;
+    c += 4.0 * steps * (double)(P.nx >> k) * (P.ny >> k);
+  }
   return c;
 }
 
-// Unit list of one sweep on level k: (slot << 16 | position), ordered by
+// Unit list of one sweep on level k over the slots whose `cont` flag equals
+// cont (and that have cells there): (slot << 16 | position), ordered by
 // position then slot (major 0) or by slot, largest grid first, then position.
-std::vector<int> make_units(const Group &G, int k, int major) {
+std::vector<int> make_units(const Group &G, int k, int major, int cont) {
   const auto &T = G.htab[k];
+  auto use = [&](int s) { return T[s].ncell > 0 && T[s].cont == cont; };
   std::vector<int> u;
   if (major == 0) {
     int maxnx = 0;
     for (const auto &e : T) maxnx = std::max(maxnx, e.A.nx);
     for (int p = 0; p < maxnx; ++p)
       for (int s = 0; s < (int)T.size(); ++s)
-        if (p < T[s].A.nx) u.push_back(s << 16 | p);
+        if (use(s) && p < T[s].A.nx) u.push_back(s << 16 | p);
   } else {
-    std::vector<int> order(T.size());
-    for (size_t s = 0; s < T.size(); ++s) order[s] = (int)s;
+    std::vector<int> order;
+    for (int s = 0; s < (int)T.size(); ++s)
+      if (use(s)) order.push_back(s);
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int c) { return T[a].ncell > T[c].ncell; });
     for (int s : order)
@@ -131,24 +137,32 @@ int upload_states(nrxx_batch *b, double *const *states) {
 
 // ---- enqueue helpers (group stream) -------------------------------------
 
-int smooth(nrxx_batch *b, Group &G, int k, int nsteps) {
+// nsteps fast-sweeping steps on level k for the problems that continue to
+// a coarser level (which = 0) or whose coarsest level k is (which = 1).
+int smooth(nrxx_batch *b, Group &G, int k, int nsteps, int which) {
+  const int U = G.U[which][k];
+  if (U == 0) return NRXX_OK;
   const int total = 4 * nsteps;
   for (int s0 = 0; s0 < total; s0 += 8) {
     const int nsw = std::min(8, total - s0);
     unsigned dirs = 0;
     for (int q = 0; q < nsw; ++q) dirs |= (unsigned)((s0 + q) & 3) << (2 * q);
     BCHK(launch_bfill(G.cnt[k], G.cntsize[k], 0, G.stream));
-    const int grid = std::max(1, std::min(G.grid, nsw * G.U[k]));
-    BCHK(launch_bsweep(G.M, G.order, G.nw, grid, G.dtab[k], G.units[G.major][k], G.U[k], nsw, dirs,
-                       G.cnt[k], b->active, b->derr, b->dabort, kWaitLimit, G.stream));
+    const int grid = std::max(1, std::min(G.grid, nsw * U));
+    BCHK(launch_bsweep(G.M, G.order, G.nw, grid, G.dtab[k], G.units[G.major][which][k], U, nsw,
+                       dirs, G.cnt[k], b->active, b->derr, b->dabort, kWaitLimit, G.stream));
   }
   return NRXX_OK;
 }
 
+// Alg. 2 on level k for every problem of the group that has level k: the
+// problems whose coarsest level this is take s3 steps; the others recurse.
 int vcycle(nrxx_batch *b, Group &G, int k) {
   const int nslot = (int)G.inst.size();
-  if (k == b->L - 1) return smooth(b, G, k, b->s3);
-  int rc = smooth(b, G, k, b->s1);
+  int rc = smooth(b, G, k, b->s3, 1);
+  if (rc) return rc;
+  if (G.U[0][k] == 0) return NRXX_OK;
+  rc = smooth(b, G, k, b->s1, 0);
   if (rc) return rc;
   BCHK(launch_bresidual(G.M, G.order, G.ncell[k], G.dtab[k], nslot, b->active, 0, nullptr, G.stream));
   BCHK(launch_brestrict(G.M, G.ncell[k + 1], G.dtab[k], G.dtab[k + 1], nslot, b->active, b->derr,
@@ -162,7 +176,7 @@ int vcycle(nrxx_batch *b, Group &G, int k) {
   }
   BCHK(launch_bcorrect(G.M, G.ncell[k + 1], G.dtab[k], G.dtab[k + 1], nslot, b->active, b->derr,
                        G.stream));
-  return smooth(b, G, k, b->s2);
+  return smooth(b, G, k, b->s2, 0);
 }
 
 int norms_enqueue(nrxx_batch *b, Group &G) {
@@ -265,13 +279,14 @@ int nrxx_batch_create(const nrxx_problem *probs, int32_t n, void *hip_stream, nr
     if (probs[i].precision != 0) return bfail(nullptr, NRXX_EINVAL, "problem %d: batches are FP64", i);
     if (probs[i].nx > 65535) return bfail(nullptr, NRXX_EINVAL, "problem %d: nx > 65535", i);
     const nrxx_problem &a = probs[0], &c = probs[i];
-    if (c.levels != a.levels || c.s1 != a.s1 || c.s2 != a.s2 || c.s3 != a.s3 || c.gamma != a.gamma)
-      return bfail(nullptr, NRXX_EINVAL, "problem %d: levels, s1, s2, s3 and gamma must be shared", i);
+    if (c.s1 != a.s1 || c.s2 != a.s2 || c.s3 != a.s3 || c.gamma != a.gamma)
+      return bfail(nullptr, NRXX_EINVAL, "problem %d: s1, s2, s3 and gamma must be shared", i);
   }
   nrxx_batch *b = new nrxx_batch();
   b->n = n;
   b->P.assign(probs, probs + n);
-  b->L = probs[0].levels;
+  b->L = 0;
+  for (int i = 0; i < n; ++i) b->L = std::max(b->L, (int)probs[i].levels);
   b->s1 = probs[0].s1;
   b->s2 = probs[0].s2;
   b->s3 = probs[0].s3;
@@ -307,19 +322,22 @@ int nrxx_batch_create(const nrxx_problem *probs, int32_t n, void *hip_stream, nr
     G.ncell.assign(L, 0);
     G.cnt.assign(L, nullptr);
     G.cntsize.assign(L, 0);
-    G.units[0].assign(L, nullptr);
-    G.units[1].assign(L, nullptr);
-    G.U.assign(L, 0);
+    for (int m = 0; m < 2; ++m)
+      for (int c = 0; c < 2; ++c) G.units[m][c].assign(L, nullptr);
+    G.U[0].assign(L, 0);
+    G.U[1].assign(L, 0);
     for (int k = 0; k < L && ok; ++k) {
       int cell0 = 0, cntn = 1;
       for (int s = 0; s < nslot; ++s) {
         const nrxx_problem &Pi = probs[G.inst[s]];
         BLevel &e = G.htab[k][s];
         e = BLevel{};
-        e.A = make_level(Pi, k);
+        e.A = make_level(Pi, std::min(k, Pi.levels - 1));
+        if (k >= Pi.levels) e.A.nx = e.A.ny = 0;  // the problem has no level k
         e.cell0 = cell0;
         e.ncell = e.A.nx * e.A.ny;
         e.inst = G.inst[s];
+        e.cont = k < Pi.levels - 1 ? 1 : 0;
         e.mass0 = Pi.mass0;
         cell0 += e.ncell;
         cntn += e.A.nx;
@@ -331,7 +349,8 @@ int nrxx_batch_create(const nrxx_problem *probs, int32_t n, void *hip_stream, nr
       for (int s = 0; s < nslot && ok; ++s) {
         BLevel &e = G.htab[k][s];
         const size_t nd = (size_t)e.ncell * G.stride * sizeof(double);
-        if (k < L - 1) e.Rbar = (double *)dalloc(G, nd);
+        if (e.ncell == 0) continue;
+        if (e.cont) e.Rbar = (double *)dalloc(G, nd);
         if (k >= 1) {
           e.st = (double *)dalloc(G, nd);
           e.rhs = (double *)dalloc(G, nd);
@@ -342,14 +361,16 @@ int nrxx_batch_create(const nrxx_problem *probs, int32_t n, void *hip_stream, nr
         off += e.A.nx;
       }
       G.dtab[k] = (BLevel *)dalloc(G, sizeof(BLevel) * nslot);
-      for (int m = 0; m < 2 && ok; ++m) {
-        std::vector<int> u = make_units(G, k, m);
-        G.U[k] = (int)u.size();
-        G.units[m][k] = (int *)dalloc(G, sizeof(int) * u.size());
-        if (ok)
-          ok = hipMemcpy(G.units[m][k], u.data(), sizeof(int) * u.size(), hipMemcpyHostToDevice) ==
-               hipSuccess;
-      }
+      for (int m = 0; m < 2 && ok; ++m)
+        for (int c = 0; c < 2 && ok; ++c) {
+          std::vector<int> u = make_units(G, k, m, c == 0 ? 1 : 0);
+          G.U[c][k] = (int)u.size();
+          if (u.empty()) continue;
+          G.units[m][c][k] = (int *)dalloc(G, sizeof(int) * u.size());
+          if (ok)
+            ok = hipMemcpy(G.units[m][c][k], u.data(), sizeof(int) * u.size(),
+                           hipMemcpyHostToDevice) == hipSuccess;
+        }
       if (ok)
         ok = hipMemcpy(G.dtab[k], G.htab[k].data(), sizeof(BLevel) * nslot, hipMemcpyHostToDevice) ==
              hipSuccess;
@@ -479,7 +500,10 @@ int nrxx_batch_sweep(nrxx_batch *b, double *const *states, int nsteps) {
   if (rc) return rc;
   rc = set_all_active(b, 1);
   if (rc) return rc;
-  rc = on_groups(b, [&](Group &G) { return smooth(b, G, 0, nsteps); });
+  rc = on_groups(b, [&](Group &G) {
+    int r = smooth(b, G, 0, nsteps, 0);
+    return r ? r : smooth(b, G, 0, nsteps, 1);
+  });
   if (rc) return rc;
   return fetch(b);
 }
@@ -603,7 +627,9 @@ int nrxx_batch_autotune(nrxx_batch *b, double *const *states) {
             ok = restore();
             if (!ok) break;
             BCHK(hipEventRecord(t0, G.stream));
-            rc = smooth(b, G, 0, std::max(1, b->s1));
+            rc = smooth(b, G, 0, std::max(1, b->s1), 0);
+            if (rc) return rc;
+            rc = smooth(b, G, 0, std::max(1, b->s1), 1);
             if (rc) return rc;
             BCHK(hipEventRecord(t1, G.stream));
             BCHK(hipEventSynchronize(t1));

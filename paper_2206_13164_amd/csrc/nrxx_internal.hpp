@@ -87,11 +87,14 @@ hipError_t launch_state_fields(int M, const LevelArgs &A, const double *st, floa
 // One instance at one level of a group (device table entry).  Level 0 `st`
 // is the caller's state; coarse `st` is f~_H.  cell0 = first cell of the
 // instance in the group's cell numbering of the level (entries sorted by it).
+// Problems may have different level counts: on levels a problem does not
+// have, its entry has no cells (ncell = 0, nx = ny = 0, no buffers); `cont`
+// is 1 where the problem continues to a coarser level (0 on its coarsest).
 struct BLevel {
   LevelArgs A;
   double *st, *rhs, *Rbar, *fbar, *RH;
   int *cnt;  // nx progress counters of the sweep kernel
-  int cell0, ncell, inst;
+  int cell0, ncell, inst, cont;
   double mass0;
 };
 bool batch_width_ok(int M, int nw);

@@ -171,13 +171,24 @@ SEED_TRAIN, SEED_TEST, SEED_INIT = 220613165, 220613166, 220613167
 SEED_BATCH = 220613164
 
 
-def cavity_draws(n: int, seed: int, sides=(64, 96, 128, 192, 256), Ms=(3, 5, 8), levels=4,
+def levels_for_side(side: int, coarsest: int = 8) -> int:
+    """Multigrid levels of a square grid: coarsen while the side is even and
+    half of it is at least `coarsest` (64 -> 4, 96 -> 4, 128 -> 5, 192 -> 5,
+    256 -> 6)."""
+    k = 1
+    while side % 2 == 0 and side // 2 >= coarsest:
+        side //= 2
+        k += 1
+    return k
+
+
+def cavity_draws(n: int, seed: int, sides=(64, 96, 128, 192, 256), Ms=(3, 5, 8), levels=None,
                  kn_range=(0.01, 1.0), lid_range=(0.1, 0.5), **overrides) -> list[dict]:
     """Lid-driven cavities with randomly drawn parameters, in the draw order
     (side, Kn, lid speed, M, collision model) per cavity: side uniform over
     `sides`, Kn log-uniform, lid speed uniform, M uniform over `Ms`, BGK or
     Shakhov (Pr 2/3) with probability 1/2; second order (central slopes),
-    walls at theta = 1."""
+    walls at theta = 1; levels from the side (levels_for_side) unless given."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(n):
@@ -187,7 +198,8 @@ def cavity_draws(n: int, seed: int, sides=(64, 96, 128, 192, 256), Ms=(3, 5, 8),
         M = int(rng.choice(Ms))
         coll = int(rng.integers(0, 2))
         d = dict(nx=side, ny=side, M=M, collision=coll, Pr=2.0 / 3.0 if coll else 1.0, Kn=kn,
-                 order=2, limiter=1, wall_u=[0.0, 0.0, lid, 0.0], levels=levels, tol=1e-8)
+                 order=2, limiter=1, wall_u=[0.0, 0.0, lid, 0.0],
+                 levels=levels if levels else levels_for_side(side), tol=1e-8)
         d.update(overrides)
         out.append(spec(None, **d))
     return out

@@ -62,8 +62,8 @@ def test_null_arguments():
 
 
 @pytest.mark.parametrize("bad", [
-    [dict(levels=2), dict(levels=3, nx=64, ny=64)],   # levels must be shared
     [dict(), dict(s1=3)],                              # smoothing steps must be shared
+    [dict(), dict(gamma=2)],                           # so must the cycle type
     [dict(), dict(precision=1)],                       # batches are FP64
     [dict(), dict(M=9)],                               # invalid member
 ])

@@ -11,14 +11,18 @@ from paper_2206_13164_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 
-def mixed_specs(levels=2):
-    base = dict(levels=levels, wall_u=[0.1, -0.15, 0.35, 0.05], wall_theta=[1.6, 1.0, 0.9, 1.2])
+def mixed_specs(levels=(2, 2, 2, 2, 2)):
+    base = dict(wall_u=[0.1, -0.15, 0.35, 0.05], wall_theta=[1.6, 1.0, 0.9, 1.2])
+    L = levels
     return [
-        I.spec(None, M=3, collision=0, Pr=1.0, order=1, nx=16, ny=12, Kn=0.3, **base),
-        I.spec(None, M=5, collision=1, Pr=2.0 / 3.0, order=2, limiter=0, nx=24, ny=16, Kn=0.1, **base),
-        I.spec(None, M=5, collision=0, Pr=1.0, order=2, limiter=1, nx=16, ny=20, Kn=0.05, **base),
-        I.spec(None, M=8, collision=1, Pr=2.0 / 3.0, order=2, limiter=1, nx=12, ny=12, Kn=0.2, **base),
-        I.spec(None, M=3, collision=1, Pr=2.0 / 3.0, order=1, nx=8, ny=24, Kn=1.0, **base),
+        I.spec(None, M=3, collision=0, Pr=1.0, order=1, nx=16, ny=12, Kn=0.3, levels=L[0], **base),
+        I.spec(None, M=5, collision=1, Pr=2.0 / 3.0, order=2, limiter=0, nx=24, ny=16, Kn=0.1,
+               levels=L[1], **base),
+        I.spec(None, M=5, collision=0, Pr=1.0, order=2, limiter=1, nx=16, ny=20, Kn=0.05,
+               levels=L[2], **base),
+        I.spec(None, M=8, collision=1, Pr=2.0 / 3.0, order=2, limiter=1, nx=12, ny=12, Kn=0.2,
+               levels=L[3], **base),
+        I.spec(None, M=3, collision=1, Pr=2.0 / 3.0, order=1, nx=8, ny=24, Kn=1.0, levels=L[4], **base),
     ]
 
 
@@ -45,7 +49,7 @@ def single_results(specs, states, fn):
 def test_batch_sweep_bitwise_equals_single_problem_sweeps():
     require_gpu()
     from paper_2206_13164_amd import nrxx as N
-    specs = mixed_specs()
+    specs = mixed_specs((2, 2, 3, 1, 2))
     b = N.Batch(specs)
     assert b.groups() == 3  # (M, order) = (3, 1), (5, 2), (8, 2)
     st0 = random_states(b, specs, 31)
@@ -67,10 +71,13 @@ def test_batch_sweep_bitwise_equals_single_problem_sweeps():
                     assert bool((st[k] == want[k]).all()), (k, width_choice, grid, order)
 
 
-def test_batch_vcycle_bitwise_equals_single_problem_vcycles():
+@pytest.mark.parametrize("levels", [(2, 2, 2, 2, 2), (3, 3, 2, 1, 3)])
+def test_batch_vcycle_bitwise_equals_single_problem_vcycles(levels):
+    # problems of one batch may have different level counts (each takes its
+    # coarsest steps on its own coarsest level)
     require_gpu()
     from paper_2206_13164_amd import nrxx as N
-    specs = mixed_specs(levels=2)
+    specs = mixed_specs(levels)
     b = N.Batch(specs)
     st = [x.clone() for x in random_states(b, specs, 41)]
     want_norms = []
@@ -91,7 +98,7 @@ def test_batch_solve_masks_graph_replays_and_cycle_counts():
     specs = [
         I.spec("lid32_bgk_m3", nx=16, ny=16),
         I.spec("lid32_bgk_m3", Kn=0.02),
-        I.spec("paper_table1_32", levels=2),
+        I.spec("paper_table1_32"),
         I.spec("lid128_shakhov_m5_central", nx=32, ny=32, levels=2),
     ]
     tol = 1e-8
