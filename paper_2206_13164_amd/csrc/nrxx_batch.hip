@@ -83,13 +83,25 @@ __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__
     const int prev = irev ? i + 1 : i - 1;
     const int pdir = s > 0 ? (dirs >> (2 * (s - 1))) & 3 : 0;
     const bool pjrev = pdir == 2 || pdir == 3;
+    if (s > 0) {
+      // the column itself has finished the previous sweep (possibly in
+      // another workgroup): its cells are read before the cross-column waits
+      if (threadIdx.x == 0) {
+        const bool ok = wait_at_least(cnt + i, s * ny, abort_flag, limit);
+        if (ok) acquire_agent();
+        sc[L::SAB] = ok ? 0.0 : 1.0;
+      }
+      __syncthreads();
+      if (sc[L::SAB] != 0.0) {
+        if (threadIdx.x == 0) atomicOr(err, 4);
+        return;  // uniform across the team
+      }
+    }
     for (int b = 0; b < ny; ++b) {
       const int j = jrev ? ny - 1 - b : b;
-      if (threadIdx.x == 0) {
+      auto wait = [&]() -> bool {
         bool ok = true;
-        // the column itself has finished the previous sweep
-        if (b == 0 && s > 0) ok = wait_at_least(cnt + i, s * ny, abort_flag, limit);
-        if (ok && p > 0) ok = wait_at_least(cnt + prev, s * ny + b + 1, abort_flag, limit);
+        if (p > 0) ok = wait_at_least(cnt + prev, s * ny + b + 1, abort_flag, limit);
         if (ok && s > 0) {
           const int bp = pjrev ? ny - 1 - j : j;
           for (int d = -2; d <= 2 && ok; ++d) {
@@ -99,15 +111,13 @@ __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__
           }
         }
         if (ok) acquire_agent();
-        sc[L::SAB] = ok ? 0.0 : 1.0;
-      }
-      __syncthreads();
-      if (sc[L::SAB] != 0.0) {
+        return ok;
+      };
+      if (!cell_team<double, M, ORDER, NW, MODE_SWEEP, true>(sA, lds, st, rhs, nullptr, nullptr,
+                                                             nullptr, i, j, err, wait)) {
         if (threadIdx.x == 0) atomicOr(err, 4);
         return;  // uniform across the team
       }
-      cell_team<double, M, ORDER, NW, MODE_SWEEP>(sA, lds, st, rhs, nullptr, nullptr, nullptr, i,
-                                                  j, err);
       if (threadIdx.x == 0)
         __hip_atomic_store(cnt + i, s * ny + b + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       __syncthreads();

@@ -566,11 +566,24 @@ __device__ __forceinline__ int face_wall(int f) { return f == 0 ? 1 : f == 1 ? 3
 //  MODE_FAS   : out = R(f) + Radd (coarse right-hand side of eq. (22)).
 // Every wavefront returns; the team's LDS may be reused after a barrier.
 // A non-physical update sets bit 0 of *err and leaves the cell unchanged.
-template <typename Real, int M, int ORDER, int NW, int MODE>
-__device__ void cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
+// With SPLIT, the team first evaluates everything that reads only the
+// cell's own grid column (the four y-direction face-side items, collision,
+// y in-cell regularisation, right-hand side), then thread 0 calls wait()
+// (which must make the neighbouring columns' data visible and return false
+// to abort), and only then the four x-direction items and the x in-cell
+// regularisation.  Each item's arithmetic and the order of assembly are the
+// same in both forms, so the results are bitwise identical; returns false
+// (uniformly) if wait() failed, leaving the cell untouched.
+struct NoWait {
+  __device__ bool operator()() const { return true; }
+};
+
+template <typename Real, int M, int ORDER, int NW, int MODE, bool SPLIT = false,
+          typename Wait = NoWait>
+__device__ bool cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
                           const Real *__restrict__ rhs, const Real *__restrict__ Radd,
                           Real *__restrict__ out, Real *__restrict__ norm_part, int i, int j,
-                          int *err) {
+                          int *err, Wait wait = Wait()) {
   using g = G<M>;
   using L = Lay<M, NW>;
   const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
@@ -597,7 +610,25 @@ __device__ void cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
       sc[L::SNU] = nu;
     }
   }
-  for (int q = wv; q < 8; q += NW) {
+  // item q = f + 4 s: face f (0 E, 1 W, 2 N, 3 S), s = 0 the cell's own face
+  // state, s = 1 the neighbour's.  Items of a pass are spread over the
+  // wavefronts: all eight in one pass, or y items (2, 3, 6, 7) then x items
+  // (0, 1, 4, 5) when split.
+  auto item_of = [&](int pass, int t) {
+    if (!SPLIT) return t;
+    const int ys[4] = {2, 3, 6, 7}, xs[4] = {0, 1, 4, 5};
+    return pass == 0 ? ys[t] : xs[t];
+  };
+  auto wave_of = [&](int pass, int t) {
+    if (!SPLIT) return t % NW;
+    return pass == 0 ? t % NW : (NW - 1 - t % NW + NW) % NW;
+  };
+  const int npass = SPLIT ? 2 : 1, nitems = SPLIT ? 4 : 8;
+
+  auto face_states = [&](int pass) {
+  for (int t = 0; t < nitems; ++t) {
+    if (wave_of(pass, t) != wv) continue;
+    const int q = item_of(pass, t);
     const int f = q & 3, s = q >> 2, D = face_dir(f);
     const Real side = (Real)face_side(f);
     const int k = D == 0 ? i : j, n = D == 0 ? nx : ny;
@@ -635,10 +666,13 @@ __device__ void cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
       sc[L::SP + 4 * q + 2] = X.th;
     }
   }
-  __syncthreads();
+  };
 
   // ---- phase 1: half-fluxes projected into the cell basis ---------------
-  for (int q = wv; q < 8; q += NW) {
+  auto fluxes = [&](int pass) {
+  for (int t = 0; t < nitems; ++t) {
+    if (wave_of(pass, t) != wv) continue;
+    const int q = item_of(pass, t);
     const int f = q & 3, s = q >> 2, D = face_dir(f);
     const Real side = (Real)face_side(f);
     const int k = D == 0 ? i : j, n = D == 0 ? nx : ny;
@@ -705,8 +739,24 @@ __device__ void cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
       if (lane == 0) sc[L::SW + f] = sd > 0 ? wm : wp;
     }
   }
-  if (wv == NW - 1) {
-    // cell-local terms on the last wavefront
+  };
+
+  // in-cell regularisation of direction D: jump between the cell's own two
+  // face states of that direction
+  auto incell_reg = [&](int D) {
+    const int fp = 2 * D, fm = 2 * D + 1;
+    const Real j1 = sc[L::SP + 4 * fp] - sc[L::SP + 4 * fm];
+    const Real j2 = sc[L::SP + 4 * fp + 1] - sc[L::SP + 4 * fm + 1];
+    const Real j3 = sc[L::SP + 4 * fp + 2] - sc[L::SP + 4 * fm + 2];
+    Real T[g::SL];
+#pragma unroll
+    for (int r = 0; r < g::SL; ++r) T[r] = regul<Real, M>(D, bC, bC, j1, j2, j3, S, r);
+    put_slots<Real, M>(lds + L::T + (L::T_GX + D) * g::SLOT, lane, T);
+  };
+
+  // cell-local terms: collision, right-hand side (and, unsplit, both
+  // in-cell regularisations; split, the y one)
+  auto local_terms = [&]() {
     const Real rho = bC[0];
     const Real nu = sc[L::SNU];
     Real T[g::SL];
@@ -728,17 +778,8 @@ __device__ void cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
     }
     put_slots<Real, M>(lds + L::T + L::T_Q * g::SLOT, lane, T);
     if (ORDER == 2) {
-      // in-cell regularisation: jump between the cell's own two face states
-#pragma unroll
-      for (int D = 0; D < 2; ++D) {
-        const int fp = 2 * D, fm = 2 * D + 1;
-        const Real j1 = sc[L::SP + 4 * fp] - sc[L::SP + 4 * fm];
-        const Real j2 = sc[L::SP + 4 * fp + 1] - sc[L::SP + 4 * fm + 1];
-        const Real j3 = sc[L::SP + 4 * fp + 2] - sc[L::SP + 4 * fm + 2];
-#pragma unroll
-        for (int r = 0; r < g::SL; ++r) T[r] = regul<Real, M>(D, bC, bC, j1, j2, j3, S, r);
-        put_slots<Real, M>(lds + L::T + (L::T_GX + D) * g::SLOT, lane, T);
-      }
+      if (!SPLIT) incell_reg(0);
+      incell_reg(1);
     }
     const Real *rr = MODE == MODE_FAS ? Radd : rhs;
     if (rr) {
@@ -756,8 +797,28 @@ __device__ void cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
       }
       put_slots<Real, M>(lds + L::T + L::T_RHS * g::SLOT, lane, T);
     }
+  };
+
+  if (!SPLIT) {
+    face_states(0);
+    __syncthreads();
+    fluxes(0);
+    if (wv == NW - 1) local_terms();
+    __syncthreads();
+  } else {
+    face_states(0);
+    __syncthreads();
+    fluxes(0);
+    if (wv == NW - 1) local_terms();
+    if (threadIdx.x == 0) sc[L::SAB] = wait() ? Real(0.0) : Real(1.0);
+    __syncthreads();
+    if (sc[L::SAB] != Real(0.0)) return false;  // uniform across the team
+    face_states(1);
+    __syncthreads();
+    fluxes(1);
+    if (ORDER == 2 && wv == (NW >= 8 ? 3 : 0)) incell_reg(0);
+    __syncthreads();
   }
-  __syncthreads();
 
   // ---- phase 2 (wavefront 0): assemble R_ij in a fixed order ------------
   if (wv == 0) {
@@ -839,6 +900,7 @@ __device__ void cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
       }
     }
   }
+  return true;
 }
 
 // Team width: 8 wavefronts (one face-side item each) while the LDS of a team

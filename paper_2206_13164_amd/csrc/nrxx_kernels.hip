@@ -47,7 +47,6 @@ __global__ __launch_bounds__(NW * WAVE) void k_sweep_persist(
     unsigned dirs, int *cnt, int base, int *err, int *abort_flag, unsigned long long limit) {
   using L = Lay<M, NW>;
   __shared__ Real lds[L::TOTAL];
-  Real *sc = lds + L::S;
   const int i = blockIdx.x;
   const int nx = A.nx, ny = A.ny;
   for (int s = 0; s < nsweep; ++s) {
@@ -60,7 +59,9 @@ __global__ __launch_bounds__(NW * WAVE) void k_sweep_persist(
     const int sbase = base + s * ny;
     for (int b = 0; b < ny; ++b) {
       const int j = jrev ? ny - 1 - b : b;
-      if (threadIdx.x == 0) {
+      // the cross-column waits run between the team's own-column half and
+      // its x-direction half (the own column is this workgroup's alone)
+      auto wait = [&]() -> bool {
         bool ok = true;
         if (hasPrev) ok = wait_at_least(cnt + prev, sbase + b + 1, abort_flag, limit);
         if (ok && s > 0) {
@@ -72,14 +73,13 @@ __global__ __launch_bounds__(NW * WAVE) void k_sweep_persist(
           }
         }
         if (ok) acquire_agent();
-        sc[L::SAB] = ok ? Real(0.0) : Real(1.0);
-      }
-      __syncthreads();
-      if (sc[L::SAB] != Real(0.0)) {
+        return ok;
+      };
+      if (!cell_team<Real, M, ORDER, NW, MODE_SWEEP, true>(A, lds, st, rhs, nullptr, nullptr,
+                                                           nullptr, i, j, err, wait)) {
         if (threadIdx.x == 0) atomicOr(err, 4);
         return;  // uniform across the team
       }
-      cell_team<Real, M, ORDER, NW, MODE_SWEEP>(A, lds, st, rhs, nullptr, nullptr, nullptr, i, j, err);
       if (threadIdx.x == 0) {
         // wavefront 0 stored the cell; publish it (agent-scope release)
         __hip_atomic_store(cnt + i, sbase + b + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
