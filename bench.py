@@ -193,7 +193,8 @@ def main():
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     ap.add_argument("--schedule", type=int, default=0,
-                    help="sweep schedule: 0 automatic, 1 per-diagonal launches, 2 persistent")
+                    help="sweep schedule: 0 automatic (= 3), 1 per-diagonal launches, "
+                         "2 static persistent, 3 work queue with overlapping sweeps")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver's "
@@ -255,7 +256,7 @@ def main():
     bytes_per_launch = ncyc * acc["bytes"] / launches
     achieved_tflops = flops_per_launch / avg_launch_s / 1e12
     achieved_gbs = bytes_per_launch / avg_launch_s / 1e9
-    kname = "k_sweep_persist" if sched == 2 else "k_sweep_diag"
+    kname = {3: "k_bsweep", 2: "k_sweep_persist"}.get(sched, "k_sweep_diag")
     traffic = profiled_traffic(kname, args.workload)
 
     out = {
@@ -289,8 +290,10 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved_tflops / PEAK_FP64_TFLOPS,
             "traffic": traffic,
-            "kernel": kname + (" (persistent: up to 16 directional sweeps of one level per launch)"
-                               if sched == 2 else " (one anti-diagonal of one sweep direction per launch)"),
+            "kernel": kname + {3: " (work queue: up to 8 overlapping directional sweeps of one level per "
+                                  "launch)",
+                               2: " (static persistent: up to 16 directional sweeps of one level per launch)"}
+                              .get(sched, " (one anti-diagonal of one sweep direction per launch)"),
             "launches": launches,
             "avg_launch_us": avg_launch_s * 1e6,
             "flops_per_launch": flops_per_launch,

@@ -94,9 +94,13 @@ typedef struct {
                              (g - g0) / s to f in FP64; residuals, restriction, coarse
                              right-hand sides, corrections and the mass fix stay FP64, so the
                              fixed point is the FP64 steady state.  Other values: NRXX_EINVAL. */
-  int32_t schedule;       /* sweep schedule: 0 = automatic (persistent where the grid's columns
-                             fit on the device at once), 1 = one launch per anti-diagonal,
-                             2 = persistent on every level (NRXX_EINVAL if impossible) */
+  int32_t schedule;       /* sweep schedule (all give the serial Gauss-Seidel result bit for bit):
+                             0 = automatic (= 3), 1 = one launch per anti-diagonal,
+                             2 = static persistent: one workgroup per grid column, all resident
+                                 at once (NRXX_EINVAL if the device cannot hold them),
+                             3 = work queue: persistent workgroups take (column, sweep) units in
+                                 dependency order; consecutive sweeps overlap, each cell waiting
+                                 only for its own stencil in the previous sweep */
 } nrxx_problem;
 
 /* Doubles per cell record for order M (N + 3 rounded up to a multiple of 8). */
@@ -120,9 +124,8 @@ const char *nrxx_last_error(const nrxx_ctx *ctx);
 int nrxx_level_shape(const nrxx_ctx *ctx, int level, int32_t *nx, int32_t *ny);
 
 /* Sweep schedule used on `level`: 1 = one launch per anti-diagonal,
- * 2 = persistent (one workgroup per grid column, cells of a column in sweep
- * order, waits on the progress of neighbouring columns).  Both give the
- * serial Gauss-Seidel result.  Negative: NRXX_EINVAL. */
+ * 2 = static persistent, 3 = work queue (see nrxx_problem.schedule).  All
+ * give the serial Gauss-Seidel result.  Negative: NRXX_EINVAL. */
 int nrxx_level_schedule(const nrxx_ctx *ctx, int level);
 
 /* Fill `state` (a level-`level` record array) with the global Maxwellian of

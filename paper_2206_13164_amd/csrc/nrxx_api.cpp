@@ -83,8 +83,15 @@ struct nrxx_ctx {
   int *dabort = nullptr;                 // abort flag of persistent sweeps
   std::vector<int *> cnt;                // per level: column progress counters
   std::vector<long long> pbase;          // per level: counter value at the next launch
-  std::vector<int> persist;              // per level: 1 = persistent sweeps
-  std::vector<int> persist32;            // per level: 1 = persistent FP32 sweeps
+  std::vector<int> persist;              // per level: 1 = static persistent sweeps
+  std::vector<int> persist32;            // per level: 1 = static persistent FP32 sweeps
+  // queue schedule (overlapping sweeps through the work-queue kernel), per
+  // level: a one-problem table, its units and its counters
+  std::vector<int> queue;                // per level: 1 = queue schedule
+  std::vector<BLevel *> qtab;
+  std::vector<int *> qunits, qcnt;
+  int *qactive = nullptr;
+  int qnw = 0, qgrid = 0, qgrid32 = 0;
   // FP32 smoothing blocks (precision 1), per level: working copy g, its
   // start g0, effective right-hand side r32, FP64 defect d64
   std::vector<float *> g32, g0_32, r32;
@@ -154,6 +161,33 @@ int check_device(nrxx_ctx *c) {
   return NRXX_OK;
 }
 
+// Directional sweeps of a level through the work-queue kernel: up to
+// kMaxSweepsPerLaunch sweeps per launch, counters cleared by a fill kernel.
+template <typename Real>
+int queue_sweeps(nrxx_ctx *c, int level, Real *st, const Real *rhs, const std::vector<int> &dirs,
+                 double *launches) {
+  const LevelArgs &A = c->lv[level];
+  const int ncnt = 1 + kMaxSweepsPerLaunch * A.nx;
+  for (size_t s0 = 0; s0 < dirs.size(); s0 += kMaxSweepsPerLaunch) {
+    const int nsw = (int)std::min<size_t>(kMaxSweepsPerLaunch, dirs.size() - s0);
+    unsigned bits = 0;
+    for (int q = 0; q < nsw; ++q) bits |= (unsigned)dirs[s0 + q] << (2 * q);
+    CHK(launch_bfill(c->qcnt[level], ncnt, 0, c->stream));
+    const int full = sizeof(Real) == 8 ? c->qgrid : c->qgrid32;
+    const int grid = std::max(1, std::min(full, nsw * A.nx));
+    if constexpr (sizeof(Real) == 8)
+      CHK(launch_bsweep(c->M, A.order, c->qnw, grid, c->qtab[level], c->qunits[level], A.nx, nsw,
+                        bits, c->qcnt[level], A.nx, c->qactive, c->derr, c->dabort, 200000000ULL,
+                        c->stream, st, rhs));
+    else
+      CHK(launch_bsweep32(c->M, A.order, c->qnw, grid, c->qtab[level], c->qunits[level], A.nx, nsw,
+                          bits, c->qcnt[level], A.nx, c->qactive, c->derr, c->dabort, 200000000ULL,
+                          c->stream, st, rhs));
+    *launches += 1.0;
+  }
+  return NRXX_OK;
+}
+
 int sweep_impl(nrxx_ctx *c, int level, double *st, const double *rhs, int mask, int nsteps) {
   const LevelArgs &A = c->lv[level];
   nrxx_ctx::Timed tm;
@@ -167,7 +201,10 @@ int sweep_impl(nrxx_ctx *c, int level, double *st, const double *rhs, int mask, 
       if (mask & (1 << k)) dirs.push_back(k);
   ndir = (int)dirs.size();
   double launches = 0.0;
-  if (c->persist[level]) {
+  if (c->queue[level]) {
+    int rc = queue_sweeps<double>(c, level, st, rhs, dirs, &launches);
+    if (rc) return rc;
+  } else if (c->persist[level]) {
     // up to 16 directional sweeps per launch (2 bits per direction)
     for (size_t s0 = 0; s0 < dirs.size(); s0 += 16) {
       const int nsw = (int)std::min<size_t>(16, dirs.size() - s0);
@@ -241,7 +278,10 @@ int sweep32_impl(nrxx_ctx *c, int level, double *st, const double *rhs, int mask
   CHK(launch_fas32(c->M, A, g0, g, r, c->stream));
   CHK(launch_to32(c->M, A, st, g, nullptr, nullptr, c->stream));
   double launches = 0.0;
-  if (c->persist32[level]) {
+  if (c->queue[level]) {
+    int rc = queue_sweeps<float>(c, level, g, r, dirs, &launches);
+    if (rc) return rc;
+  } else if (c->persist32[level]) {
     for (size_t s0 = 0; s0 < dirs.size(); s0 += 16) {
       const int nsw = (int)std::min<size_t>(16, dirs.size() - s0);
       unsigned bits = 0;
@@ -350,7 +390,7 @@ bool validate_problem(const nrxx_problem &P, std::string &msg) {
     return bad(msg, "bad smoothing steps or gamma");
   if (P.precision != 0 && P.precision != 1)
     return bad(msg, "precision = %d not supported", P.precision);
-  if (P.schedule < 0 || P.schedule > 2) return bad(msg, "schedule = %d", P.schedule);
+  if (P.schedule < 0 || P.schedule > 3) return bad(msg, "schedule = %d", P.schedule);
   if ((long long)P.nx * P.ny > (1LL << 26)) return bad(msg, "grid too large");
 
   return true;
@@ -433,6 +473,10 @@ int nrxx_create(const nrxx_problem *p, void *hip_stream, nrxx_ctx **out) {
   c->pbase.assign(c->L, 0);
   c->persist.assign(c->L, 0);
   c->persist32.assign(c->L, 0);
+  c->queue.assign(c->L, 0);
+  c->qtab.assign(c->L, nullptr);
+  c->qunits.assign(c->L, nullptr);
+  c->qcnt.assign(c->L, nullptr);
   c->g32.assign(c->L, nullptr);
   c->g0_32.assign(c->L, nullptr);
   c->r32.assign(c->L, nullptr);
@@ -463,13 +507,46 @@ int nrxx_create(const nrxx_problem *p, void *hip_stream, nrxx_ctx **out) {
     nrxx_destroy(c);
     return fail(nullptr, NRXX_EHIP, "stream unusable");
   }
-  // sweep schedule per level: persistent (one workgroup per column, all
-  // resident at once) or one launch per anti-diagonal
-  const int maxcols = P.schedule == 1 ? 0 : persist_max_columns(P.M, P.order);
-  const int maxcols32 = (P.schedule == 1 || P.precision != 1) ? 0 : persist_max_columns32(P.M, P.order);
+  // sweep schedule per level: the work-queue kernel with overlapping
+  // sweeps (automatic or 3), static persistent (one workgroup per column,
+  // all resident at once; 2) or one launch per anti-diagonal (1)
+  if (P.schedule == 0 || P.schedule == 3) {
+    c->qnw = P.M <= 5 ? 8 : 2;
+    c->qgrid = bsweep_resident(P.M, P.order, c->qnw);
+    c->qgrid32 = P.precision == 1 ? bsweep_resident32(P.M, P.order, c->qnw) : 1;
+    bool qok = c->qgrid >= 1 && c->qgrid32 >= 1 &&
+               hipMalloc((void **)&c->qactive, sizeof(int)) == hipSuccess;
+    const int one = 1;
+    if (qok) qok = hipMemcpy(c->qactive, &one, sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+    for (int k = 0; k < c->L && qok; ++k) {
+      const LevelArgs &A = c->lv[k];
+      qok = hipMalloc((void **)&c->qtab[k], sizeof(BLevel)) == hipSuccess &&
+            hipMalloc((void **)&c->qunits[k], sizeof(int) * A.nx) == hipSuccess &&
+            hipMalloc((void **)&c->qcnt[k], sizeof(int) * (1 + kMaxSweepsPerLaunch * A.nx)) == hipSuccess;
+      if (!qok) break;
+      BLevel e{};
+      e.A = A;
+      e.cnt = c->qcnt[k] + 1;
+      e.ncell = A.nx * A.ny;
+      e.cont = k < c->L - 1 ? 1 : 0;
+      e.mass0 = P.mass0;
+      std::vector<int> u(A.nx);
+      for (int p = 0; p < A.nx; ++p) u[p] = p;  // slot 0, position p
+      qok = hipMemcpy(c->qtab[k], &e, sizeof(BLevel), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(c->qunits[k], u.data(), sizeof(int) * A.nx, hipMemcpyHostToDevice) == hipSuccess;
+      c->queue[k] = 1;
+    }
+    if (!qok) {
+      nrxx_destroy(c);
+      return fail(nullptr, NRXX_ENOMEM, "queue schedule set-up failed");
+    }
+  }
+  const bool static_ok = P.schedule == 2;
+  const int maxcols = static_ok ? persist_max_columns(P.M, P.order) : 0;
+  const int maxcols32 = (static_ok && P.precision == 1) ? persist_max_columns32(P.M, P.order) : 0;
   for (int k = 0; k < c->L; ++k) {
-    c->persist[k] = P.schedule != 1 && c->lv[k].nx <= maxcols;
-    c->persist32[k] = P.precision == 1 && P.schedule != 1 && c->lv[k].nx <= maxcols32;
+    c->persist[k] = static_ok && c->lv[k].nx <= maxcols;
+    c->persist32[k] = P.precision == 1 && static_ok && c->lv[k].nx <= maxcols32;
     if (P.schedule == 2 && P.precision == 1 && !c->persist32[k]) {
       nrxx_destroy(c);
       return fail(nullptr, NRXX_EINVAL, "persistent FP32 sweeps do not fit on the device");
@@ -506,6 +583,12 @@ int nrxx_destroy(nrxx_ctx *c) {
   for (double *p : c->d64)
     if (p) (void)hipFree(p);
   if (c->dblk) (void)hipFree(c->dblk);
+  for (auto *v : {&c->qunits, &c->qcnt})
+    for (int *p : *v)
+      if (p) (void)hipFree(p);
+  for (BLevel *p : c->qtab)
+    if (p) (void)hipFree(p);
+  if (c->qactive) (void)hipFree(c->qactive);
   if (c->hscal) (void)hipHostFree(c->hscal);
   delete c;
   return NRXX_OK;
@@ -522,7 +605,7 @@ int nrxx_level_shape(const nrxx_ctx *c, int level, int32_t *nx, int32_t *ny) {
 
 int nrxx_level_schedule(const nrxx_ctx *c, int level) {
   if (!level_ok(c, level)) return NRXX_EINVAL;
-  return c->persist[level] ? 2 : 1;
+  return c->queue[level] ? 3 : c->persist[level] ? 2 : 1;
 }
 
 int nrxx_init_maxwellian(nrxx_ctx *c, int level, double *state, double rho, double u1, double u2,

@@ -46,17 +46,34 @@ __device__ __forceinline__ void stage_args(const LevelArgs &src, LevelArgs &dst)
   __syncthreads();
 }
 
-template <int M, int ORDER, int NW>
+// Progress counters: cnt[s * cstride + c] = rows of column c finished in
+// sweep s of this launch (zero at launch).  Cell (i, j) of sweep s waits for
+//  (own) rows j-2 .. j+2 of its own column finished in sweep s-1: its own
+//        stencil holds their final values and nothing still reads its old one
+//        -- the column's previous sweep may still be running in another
+//        workgroup, so consecutive sweeps overlap instead of waiting for
+//        whole columns;
+//  (up)  the previous column of sweep s finished row j;
+//  (nb)  columns i-2 .. i+2 finished row j in sweep s-1.
+// These are exactly the serial order's requirements for a radius-2
+// cross-shaped stencil.  The own-column wait comes first (the team then reads
+// its own column), the others between the two halves of the cell team.
+// With st_ovr non-null (one problem, the single-problem library), its state
+// and right-hand side replace the table's pointers; this is also how FP32
+// records (Real = float) are swept.
+template <typename Real, int M, int ORDER, int NW>
 __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__ tab,
                                                       const int *__restrict__ units, int U,
                                                       int nsweep, unsigned dirs, int *queue,
-                                                      const int *__restrict__ active, int *err,
-                                                      int *abort_flag, unsigned long long limit) {
+                                                      int cstride, const int *__restrict__ active,
+                                                      int *err, int *abort_flag,
+                                                      unsigned long long limit, Real *st_ovr,
+                                                      const Real *rhs_ovr) {
   using L = Lay<M, NW>;
-  __shared__ double lds[L::TOTAL];
+  __shared__ Real lds[L::TOTAL];
   __shared__ int su;
   __shared__ LevelArgs sA;
-  double *sc = lds + L::S;
+  Real *sc = lds + L::S;
   const int total = nsweep * U;
   for (;;) {
     if (threadIdx.x == 0) {
@@ -73,53 +90,61 @@ __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__
     const BLevel &B = tab[slot];
     if (!active[B.inst]) continue;
     stage_args(B.A, sA);
-    double *const st = B.st;
-    const double *const rhs = B.rhs;
+    Real *const st = st_ovr ? st_ovr : reinterpret_cast<Real *>(B.st);
+    const Real *const rhs = st_ovr ? rhs_ovr : reinterpret_cast<const Real *>(B.rhs);
     const int nx = sA.nx, ny = sA.ny;
-    int *cnt = B.cnt;
+    int *cs = B.cnt + s * cstride;                 // this sweep's counters
+    int *cp = s > 0 ? cs - cstride : nullptr;      // previous sweep's
     const int dir = (dirs >> (2 * s)) & 3;
     const bool irev = dir == 1 || dir == 2, jrev = dir == 2 || dir == 3;
     const int i = irev ? nx - 1 - p : p;
     const int prev = irev ? i + 1 : i - 1;
     const int pdir = s > 0 ? (dirs >> (2 * (s - 1))) & 3 : 0;
     const bool pjrev = pdir == 2 || pdir == 3;
-    if (s > 0) {
-      // the column itself has finished the previous sweep (possibly in
-      // another workgroup): its cells are read before the cross-column waits
-      if (threadIdx.x == 0) {
-        const bool ok = wait_at_least(cnt + i, s * ny, abort_flag, limit);
-        if (ok) acquire_agent();
-        sc[L::SAB] = ok ? 0.0 : 1.0;
-      }
-      __syncthreads();
-      if (sc[L::SAB] != 0.0) {
-        if (threadIdx.x == 0) atomicOr(err, 4);
-        return;  // uniform across the team
-      }
-    }
+    int known = 0;  // rows of the own column known finished in sweep s-1 (thread 0)
     for (int b = 0; b < ny; ++b) {
       const int j = jrev ? ny - 1 - b : b;
+      if (s > 0) {
+        if (threadIdx.x == 0) {
+          const int need = pjrev ? ny - (j - 2 > 0 ? j - 2 : 0) : (j + 2 < ny - 1 ? j + 2 : ny - 1) + 1;
+          bool ok = true;
+          if (known < need) {
+            ok = wait_at_least(cp + i, need, abort_flag, limit);
+            if (ok) {
+              acquire_agent();
+              known = __hip_atomic_load(cp + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              if (known < need) known = need;
+            }
+          }
+          sc[L::SAB] = ok ? Real(0.0) : Real(1.0);
+        }
+        __syncthreads();
+        if (sc[L::SAB] != Real(0.0)) {
+          if (threadIdx.x == 0) atomicOr(err, 4);
+          return;  // uniform across the team
+        }
+      }
       auto wait = [&]() -> bool {
         bool ok = true;
-        if (p > 0) ok = wait_at_least(cnt + prev, s * ny + b + 1, abort_flag, limit);
+        if (p > 0) ok = wait_at_least(cs + prev, b + 1, abort_flag, limit);
         if (ok && s > 0) {
           const int bp = pjrev ? ny - 1 - j : j;
           for (int d = -2; d <= 2 && ok; ++d) {
             const int ii = i + d;
             if (d == 0 || ii < 0 || ii >= nx) continue;
-            ok = wait_at_least(cnt + ii, (s - 1) * ny + bp + 1, abort_flag, limit);
+            ok = wait_at_least(cp + ii, bp + 1, abort_flag, limit);
           }
         }
         if (ok) acquire_agent();
         return ok;
       };
-      if (!cell_team<double, M, ORDER, NW, MODE_SWEEP, true>(sA, lds, st, rhs, nullptr, nullptr,
-                                                             nullptr, i, j, err, wait)) {
+      if (!cell_team<Real, M, ORDER, NW, MODE_SWEEP, true>(sA, lds, st, rhs, nullptr, nullptr,
+                                                           nullptr, i, j, err, wait)) {
         if (threadIdx.x == 0) atomicOr(err, 4);
         return;  // uniform across the team
       }
       if (threadIdx.x == 0)
-        __hip_atomic_store(cnt + i, s * ny + b + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(cs + i, b + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       __syncthreads();
     }
   }
@@ -265,8 +290,8 @@ bool batch_width_ok(int M, int nw) {
 int batch_default_width(int M) { return M <= 5 ? 8 : 4; }
 
 #define NRXX_BSWEEP(MM, OO, NWV)                                                                   \
-  hipLaunchKernelGGL((k_bsweep<MM, OO, NWV>), dim3(grid), dim3(NWV * WAVE), 0, s, tab, units, U,   \
-                     nsweep, dirs, queue, active, err, abort_flag, limit)
+  hipLaunchKernelGGL((k_bsweep<Real, MM, OO, NWV>), dim3(grid), dim3(NWV * WAVE), 0, s, tab, units, \
+                     U, nsweep, dirs, queue, cstride, active, err, abort_flag, limit, st_ovr, rhs_ovr)
 #define NRXX_BSWEEP_W(MM, OO)                   \
   switch (nw) {                                 \
     case 1: NRXX_BSWEEP(MM, OO, 1); break;      \
@@ -283,24 +308,25 @@ struct BigW {
   static constexpr int W = M <= 5 ? 8 : 4;
 };
 
-template <int M, int ORDER>
+template <typename Real, int M, int ORDER>
 int occupancy_of(int nw, int *per) {
   hipError_t e;
   switch (nw) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_bsweep<M, ORDER, 1>, WAVE, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_bsweep<M, ORDER, 2>, 2 * WAVE, 0); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_bsweep<M, ORDER, 4>, 4 * WAVE, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_bsweep<Real, M, ORDER, 1>, WAVE, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_bsweep<Real, M, ORDER, 2>, 2 * WAVE, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_bsweep<Real, M, ORDER, 4>, 4 * WAVE, 0); break;
     default:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_bsweep<M, ORDER, BigW<M>::W>,
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_bsweep<Real, M, ORDER, BigW<M>::W>,
                                                        BigW<M>::W * WAVE, 0);
   }
   return e == hipSuccess ? 0 : -1;
 }
-}  // namespace
 
-hipError_t launch_bsweep(int M, int order, int nw, int grid, const BLevel *tab, const int *units,
-                         int U, int nsweep, unsigned dirs, int *queue, const int *active, int *err,
-                         int *abort_flag, unsigned long long limit, hipStream_t s) {
+template <typename Real>
+hipError_t launch_bsweep_t(int M, int order, int nw, int grid, const BLevel *tab, const int *units,
+                           int U, int nsweep, unsigned dirs, int *queue, int cstride,
+                           const int *active, int *err, int *abort_flag, unsigned long long limit,
+                           hipStream_t s, Real *st_ovr, const Real *rhs_ovr) {
   if (!batch_width_ok(M, nw) || grid < 1) return hipErrorInvalidValue;
   NRXX_DISPATCH_M(M, {
     if (order == 1) {
@@ -311,10 +337,9 @@ hipError_t launch_bsweep(int M, int order, int nw, int grid, const BLevel *tab, 
   });
   return hipGetLastError();
 }
-#undef NRXX_BSWEEP_W
-#undef NRXX_BSWEEP
 
-int bsweep_resident(int M, int order, int nw) {
+template <typename Real>
+int resident_t(int M, int order, int nw) {
   int dev = 0, ncu = 0, per = 0;
   if (!batch_width_ok(M, nw)) return 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -322,7 +347,7 @@ int bsweep_resident(int M, int order, int nw) {
   int rc = -1;
   switch (M) {
 #define NRXX_OCC(MM) \
-    case MM: rc = order == 1 ? occupancy_of<MM, 1>(nw, &per) : occupancy_of<MM, 2>(nw, &per); break;
+    case MM: rc = order == 1 ? occupancy_of<Real, MM, 1>(nw, &per) : occupancy_of<Real, MM, 2>(nw, &per); break;
     NRXX_OCC(3) NRXX_OCC(4) NRXX_OCC(5) NRXX_OCC(6) NRXX_OCC(7) NRXX_OCC(8)
 #undef NRXX_OCC
     default: return 0;
@@ -330,6 +355,28 @@ int bsweep_resident(int M, int order, int nw) {
   if (rc) return 0;
   return per * ncu;
 }
+}  // namespace
+#undef NRXX_BSWEEP_W
+#undef NRXX_BSWEEP
+
+hipError_t launch_bsweep(int M, int order, int nw, int grid, const BLevel *tab, const int *units,
+                         int U, int nsweep, unsigned dirs, int *queue, int cstride,
+                         const int *active, int *err, int *abort_flag, unsigned long long limit,
+                         hipStream_t s, double *st_ovr, const double *rhs_ovr) {
+  return launch_bsweep_t<double>(M, order, nw, grid, tab, units, U, nsweep, dirs, queue, cstride,
+                                 active, err, abort_flag, limit, s, st_ovr, rhs_ovr);
+}
+
+hipError_t launch_bsweep32(int M, int order, int nw, int grid, const BLevel *tab, const int *units,
+                           int U, int nsweep, unsigned dirs, int *queue, int cstride,
+                           const int *active, int *err, int *abort_flag, unsigned long long limit,
+                           hipStream_t s, float *st, const float *rhs) {
+  return launch_bsweep_t<float>(M, order, nw, grid, tab, units, U, nsweep, dirs, queue, cstride,
+                                active, err, abort_flag, limit, s, st, rhs);
+}
+
+int bsweep_resident(int M, int order, int nw) { return resident_t<double>(M, order, nw); }
+int bsweep_resident32(int M, int order, int nw) { return resident_t<float>(M, order, nw); }
 
 hipError_t launch_bresidual(int M, int order, int ncell, const BLevel *tab, int nslot,
                             const int *active, int role, double *partial, hipStream_t s) {

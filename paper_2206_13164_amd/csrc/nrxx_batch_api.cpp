@@ -26,8 +26,8 @@ struct nrxx_batch {
     std::vector<std::vector<BLevel>> htab;  // [level][slot]
     std::vector<BLevel *> dtab;             // device copies
     std::vector<int> ncell;                 // cells of the group per level
-    std::vector<int *> cnt;                 // [queue | counters of every slot]
-    std::vector<int> cntsize;
+    std::vector<int *> cnt;                 // [queue | per sweep: counters of every slot]
+    std::vector<int> cntsize, cols;         // cols = columns of the group per level
     // unit lists per unit order, per level, for the problems that continue
     // to a coarser level (c = 0) and for those whose coarsest level it is (1)
     std::vector<int *> units[2][2];
@@ -143,14 +143,15 @@ int smooth(nrxx_batch *b, Group &G, int k, int nsteps, int which) {
   const int U = G.U[which][k];
   if (U == 0) return NRXX_OK;
   const int total = 4 * nsteps;
-  for (int s0 = 0; s0 < total; s0 += 8) {
-    const int nsw = std::min(8, total - s0);
+  for (int s0 = 0; s0 < total; s0 += kMaxSweepsPerLaunch) {
+    const int nsw = std::min(kMaxSweepsPerLaunch, total - s0);
     unsigned dirs = 0;
     for (int q = 0; q < nsw; ++q) dirs |= (unsigned)((s0 + q) & 3) << (2 * q);
     BCHK(launch_bfill(G.cnt[k], G.cntsize[k], 0, G.stream));
     const int grid = std::max(1, std::min(G.grid, nsw * U));
     BCHK(launch_bsweep(G.M, G.order, G.nw, grid, G.dtab[k], G.units[G.major][which][k], U, nsw,
-                       dirs, G.cnt[k], b->active, b->derr, b->dabort, kWaitLimit, G.stream));
+                       dirs, G.cnt[k], G.cols[k], b->active, b->derr, b->dabort, kWaitLimit,
+                       G.stream));
   }
   return NRXX_OK;
 }
@@ -322,12 +323,13 @@ int nrxx_batch_create(const nrxx_problem *probs, int32_t n, void *hip_stream, nr
     G.ncell.assign(L, 0);
     G.cnt.assign(L, nullptr);
     G.cntsize.assign(L, 0);
+    G.cols.assign(L, 0);
     for (int m = 0; m < 2; ++m)
       for (int c = 0; c < 2; ++c) G.units[m][c].assign(L, nullptr);
     G.U[0].assign(L, 0);
     G.U[1].assign(L, 0);
     for (int k = 0; k < L && ok; ++k) {
-      int cell0 = 0, cntn = 1;
+      int cell0 = 0, cols = 0;
       for (int s = 0; s < nslot; ++s) {
         const nrxx_problem &Pi = probs[G.inst[s]];
         BLevel &e = G.htab[k][s];
@@ -340,11 +342,12 @@ int nrxx_batch_create(const nrxx_problem *probs, int32_t n, void *hip_stream, nr
         e.cont = k < Pi.levels - 1 ? 1 : 0;
         e.mass0 = Pi.mass0;
         cell0 += e.ncell;
-        cntn += e.A.nx;
+        cols += e.A.nx;
       }
       G.ncell[k] = cell0;
-      G.cntsize[k] = cntn;
-      G.cnt[k] = (int *)dalloc(G, sizeof(int) * cntn);
+      G.cols[k] = cols;
+      G.cntsize[k] = 1 + kMaxSweepsPerLaunch * cols;
+      G.cnt[k] = (int *)dalloc(G, sizeof(int) * G.cntsize[k]);
       int off = 1;
       for (int s = 0; s < nslot && ok; ++s) {
         BLevel &e = G.htab[k][s];

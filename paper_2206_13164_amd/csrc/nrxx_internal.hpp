@@ -100,12 +100,23 @@ struct BLevel {
 bool batch_width_ok(int M, int nw);
 int batch_default_width(int M);
 // Persistent work-queue sweeps: units[U] = (slot << 16 | column position),
-// nsweep sweeps (2 direction bits each in dirs); *queue and every instance's
+// nsweep <= 8 sweeps (2 direction bits each in dirs).  Counters: a problem's
+// entry `cnt` points at its first column's counter of sweep 0; sweep s's are
+// cstride further (cstride = columns of the whole group); *queue and all
 // counters must be zero at launch.
+// st_ovr / rhs_ovr (non-null: a one-problem table) replace the table's
+// state and right-hand side; launch_bsweep32 sweeps FP32 records that way.
+constexpr int kMaxSweepsPerLaunch = 8;
 hipError_t launch_bsweep(int M, int order, int nw, int grid, const BLevel *tab, const int *units,
-                         int U, int nsweep, unsigned dirs, int *queue, const int *active, int *err,
-                         int *abort_flag, unsigned long long limit, hipStream_t s);
+                         int U, int nsweep, unsigned dirs, int *queue, int cstride,
+                         const int *active, int *err, int *abort_flag, unsigned long long limit,
+                         hipStream_t s, double *st_ovr = nullptr, const double *rhs_ovr = nullptr);
+hipError_t launch_bsweep32(int M, int order, int nw, int grid, const BLevel *tab, const int *units,
+                           int U, int nsweep, unsigned dirs, int *queue, int cstride,
+                           const int *active, int *err, int *abort_flag, unsigned long long limit,
+                           hipStream_t s, float *st, const float *rhs);
 int bsweep_resident(int M, int order, int nw);
+int bsweep_resident32(int M, int order, int nw);
 // role 0: Rbar = rhs - R(st); 1: rhs = R(fbar) + RH; 2: partial = weighted squares
 hipError_t launch_bresidual(int M, int order, int ncell, const BLevel *tab, int nslot,
                             const int *active, int role, double *partial, hipStream_t s);

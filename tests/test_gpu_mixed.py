@@ -49,7 +49,7 @@ def test_mixed_solve_matches_fp64_oracle_config1(orc):
     assert err < 1e-8
 
 
-@pytest.mark.parametrize("schedule", [1, 2])
+@pytest.mark.parametrize("schedule", [1, 3])
 def test_mixed_heated_cavity_reduced(schedule):
     # config-3 physics (bottom-heated, Shakhov, Kn 0.05, M = 8, 2nd order) on
     # 32x32 with 3 levels: residual 1e-8 reached, x-mirror symmetric, and the
@@ -75,19 +75,20 @@ def test_mixed_heated_cavity_reduced(schedule):
 
 
 def test_mixed_schedules_agree_bitwise():
-    # FP32 persistent and per-diagonal sweeps give identical blocks
+    # FP32 queue, static persistent and per-diagonal sweeps give identical blocks
     require_gpu()
     for M, coll, order in ((3, 0, 1), (5, 1, 2), (8, 1, 2)):
         s = I.spec(None, M=M, collision=coll, Pr=2.0 / 3.0 if coll else 1.0, order=order,
                    nx=16, ny=12, levels=2, Kn=0.15, wall_u=[0.1, -0.15, 0.35, 0.05],
                    wall_theta=[1.6, 1.0, 0.9, 1.2], precision=1)
-        ca, cb = context(dict(s, schedule=1)), context(dict(s, schedule=2))
-        assert cb.level_schedule(0) == 2
+        ca, cb, cq = (context(dict(s, schedule=k)) for k in (1, 2, 3))
+        assert cb.level_schedule(0) == 2 and cq.level_schedule(0) == 3
         st = I.random_state(s, seed=23, amp=0.06)
-        a, b = ca.to_device(st), cb.to_device(st)
+        a, b, q = ca.to_device(st), cb.to_device(st), cq.to_device(st)
         ca.sweep(a, nsteps=2)
         cb.sweep(b, nsteps=2)
-        assert bool((a == b).all()), M
+        cq.sweep(q, nsteps=2)
+        assert bool((a == b).all()) and bool((a == q).all()), M
 
 
 def test_mixed_first_block_close_to_fp64_sweep():

@@ -281,23 +281,30 @@ def test_persistent_and_diagonal_schedules_agree_bitwise(orc, case):
     s = small_spec(*case, nx=16, ny=12, levels=2)
     ctx_d = context(dict(s, schedule=1))
     ctx_p = context(dict(s, schedule=2))
+    ctx_q = context(dict(s, schedule=3))
     assert ctx_d.level_schedule(0) == 1 and ctx_p.level_schedule(0) == 2
+    assert ctx_q.level_schedule(0) == 3 and context(s).level_schedule(1) == 3
     st = I.random_state(s, seed=17, amp=0.06)
-    a, b = ctx_d.to_device(st), ctx_p.to_device(st)
+    a, b, q = ctx_d.to_device(st), ctx_p.to_device(st), ctx_q.to_device(st)
     ctx_d.sweep(a, dir_mask=15, nsteps=2)
     ctx_p.sweep(b, dir_mask=15, nsteps=2)
-    assert bool((a == b).all())
+    ctx_q.sweep(q, dir_mask=15, nsteps=2)
+    assert bool((a == b).all()) and bool((a == q).all())
     for mask in (1, 6, 9, 11):
         ctx_d.sweep(a, dir_mask=mask)
         ctx_p.sweep(b, dir_mask=mask)
-        assert bool((a == b).all()), mask
+        ctx_q.sweep(q, dir_mask=mask, nsteps=3)
+        ctx_d.sweep(a, dir_mask=mask, nsteps=2)
+        ctx_p.sweep(b, dir_mask=mask, nsteps=2)
+        assert bool((a == b).all()) and bool((a == q).all()), mask
     # coarse level with a right-hand side
     c = I.random_state(s, level=1, seed=18, amp=0.06)
     r = I.random_rhs(s, 1, seed=19)
-    ca, cb, rd = ctx_d.to_device(c), ctx_p.to_device(c), ctx_d.to_device(r)
+    ca, cb, cq, rd = ctx_d.to_device(c), ctx_p.to_device(c), ctx_q.to_device(c), ctx_d.to_device(r)
     ctx_d.sweep(ca, level=1, rhs=rd, nsteps=3)
     ctx_p.sweep(cb, level=1, rhs=rd, nsteps=3)
-    assert bool((ca == cb).all())
+    ctx_q.sweep(cq, level=1, rhs=rd, nsteps=3)
+    assert bool((ca == cb).all()) and bool((ca == cq).all())
     # and whole V-cycles
     for _ in range(2):
         na = ctx_d.fas_vcycle(a)
