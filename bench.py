@@ -21,7 +21,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "smoother cell-moment updates/s + time-to-residual 1e-8, plain vs mixed/learned"
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2206_13164_amd", "csrc", f)
-               for f in ("nrxx_device.hpp", "nrxx_kernels.hip")]
+               for f in ("nrxx_device.hpp", "nrxx_kernels.hip", "nrxx_batch.hip")]
 PROFILES = os.path.join(ROOT, "profiles")
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
@@ -58,7 +58,7 @@ def cycle_accounting(spec):
 
 
 def kernel_source_hash() -> str:
-    """sha256 over the sources of the single-problem kernels."""
+    """sha256 over the sources of the sweep kernels."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SRCS:

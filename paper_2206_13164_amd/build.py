@@ -15,6 +15,10 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions are disabled for every HIP translation unit
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # contract a*b+c into FMA only within one source expression, so the same
+    # cell arithmetic rounds the same way in every kernel it is inlined into
+    # (the sweep schedules are compared bit for bit)
+    "-ffp-contract=on",
     "-Wno-unused-command-line-argument",
 ]
 

@@ -614,21 +614,27 @@ __device__ bool cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
   // state, s = 1 the neighbour's.  Items of a pass are spread over the
   // wavefronts: all eight in one pass, or y items (2, 3, 6, 7) then x items
   // (0, 1, 4, 5) when split.
-  auto item_of = [&](int pass, int t) {
-    if (!SPLIT) return t;
-    const int ys[4] = {2, 3, 6, 7}, xs[4] = {0, 1, 4, 5};
-    return pass == 0 ? ys[t] : xs[t];
+  // Unsplit, wavefront wv takes items wv, wv + NW, ... in a run-time loop
+  // (one copy of the item code keeps register use low for the many-cell
+  // kernels).  Split, pass 0 spreads the y items 2, 3, 6, 7 over wavefronts
+  // 0, 1, 2, 3 (mod NW) and pass 1 the x items 0, 1, 4, 5 over wavefronts
+  // NW-1, NW-2, ... (mod NW), unrolled.
+  auto for_items = [&](int pass, auto &&body) {
+    if constexpr (SPLIT) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int w = pass == 0 ? t % NW : (NW - 1 - t % NW + NW) % NW;
+        if (w != wv) continue;
+        body(pass == 0 ? (t < 2 ? 2 + t : 4 + t) : (t < 2 ? t : 2 + t));
+      }
+    } else {
+#pragma unroll 1
+      for (int q = wv; q < 8; q += NW) body(q);
+    }
   };
-  auto wave_of = [&](int pass, int t) {
-    if (!SPLIT) return t % NW;
-    return pass == 0 ? t % NW : (NW - 1 - t % NW + NW) % NW;
-  };
-  const int npass = SPLIT ? 2 : 1, nitems = SPLIT ? 4 : 8;
 
   auto face_states = [&](int pass) {
-  for (int t = 0; t < nitems; ++t) {
-    if (wave_of(pass, t) != wv) continue;
-    const int q = item_of(pass, t);
+  for_items(pass, [&](const int q) {
     const int f = q & 3, s = q >> 2, D = face_dir(f);
     const Real side = (Real)face_side(f);
     const int k = D == 0 ? i : j, n = D == 0 ? nx : ny;
@@ -645,7 +651,7 @@ __device__ bool cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
         face_state<Real, M>(c, hi, lo, A.limiter, false, side, X);
       }
     } else {
-      if (wall) continue;
+      if (wall) return;
       const int kn = k + sd;
       const bool nflat = ORDER == 1 || kn == 0 || kn == n - 1;
       Cell<Real, M> nb;
@@ -665,14 +671,12 @@ __device__ bool cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
       sc[L::SP + 4 * q + 1] = X.u2;
       sc[L::SP + 4 * q + 2] = X.th;
     }
-  }
+  });
   };
 
   // ---- phase 1: half-fluxes projected into the cell basis ---------------
   auto fluxes = [&](int pass) {
-  for (int t = 0; t < nitems; ++t) {
-    if (wave_of(pass, t) != wv) continue;
-    const int q = item_of(pass, t);
+  for_items(pass, [&](const int q) {
     const int f = q & 3, s = q >> 2, D = face_dir(f);
     const Real side = (Real)face_side(f);
     const int k = D == 0 ? i : j, n = D == 0 ? nx : ny;
@@ -680,10 +684,10 @@ __device__ bool cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
     const bool wall = (k + sd < 0) || (k + sd >= n);
     Real T[g::SL];
     if (wall) {
-      if (s == 1) continue;
+      if (s == 1) return;
       wall_flux<Real, M>(A, face_wall(f), c.u1, c.u2, c.th, bC, W, T);
       put_slots<Real, M>(lds + L::T + q * g::SLOT, lane, T);
-      continue;
+      return;
     }
     // L / R face states: the cell is left of its E and N faces
     const int qo = f, qn = f + 4;
@@ -738,7 +742,7 @@ __device__ bool cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
       put_slots<Real, M>(lds + L::GR + f * g::SLOT, lane, gr);
       if (lane == 0) sc[L::SW + f] = sd > 0 ? wm : wp;
     }
-  }
+  });
   };
 
   // in-cell regularisation of direction D: jump between the cell's own two
