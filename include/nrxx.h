@@ -199,6 +199,13 @@ int nrxx_solve(nrxx_ctx *ctx, double *state, double tol, int max_cycles, double 
 int nrxx_sweep_stats(nrxx_ctx *ctx, double *ms_out, double *cell_updates_out,
                      double *launches_out, int reset);
 
+/* Bound (seconds, 1e-8 .. 3600; default 2) on any single wait of a
+ * persistent sweep kernel for a neighbouring column.  A wait that exceeds it
+ * makes every workgroup of the launch give up, so the kernel always ends; the
+ * next synchronising call returns NRXX_EHIP and the state then holds a
+ * partially completed sweep.  The context stays usable. */
+int nrxx_set_wait_limit(nrxx_ctx *ctx, double seconds);
+
 /* ---------------------------------------------------------------------------
  * Batches: many independent problems solved together on one device.
  *
@@ -265,6 +272,9 @@ int nrxx_batch_vcycle(nrxx_batch *b, double *const *states, double *norms_out);
  * every problem converged, NRXX_EMAXIT otherwise (states valid). */
 int nrxx_batch_solve(nrxx_batch *b, double *const *states, double tol, int32_t max_cycles,
                      int32_t use_graph, int32_t *cycles_out, double *norms_out, double *ref_out);
+/* As nrxx_set_wait_limit, for the batch's sweep kernels (drops captured
+ * graphs). */
+int nrxx_batch_set_wait_limit(nrxx_batch *b, double seconds);
 /* Device time (ms) of the batch's V-cycles and the cell updates their sweeps
  * made since creation or the last reset. */
 int nrxx_batch_stats(nrxx_batch *b, double *ms_out, double *cell_updates_out, int reset);

@@ -92,6 +92,7 @@ struct nrxx_ctx {
   std::vector<int *> qunits, qcnt;
   int *qactive = nullptr;
   int qnw = 0, qgrid = 0, qgrid32 = 0;
+  unsigned long long wait_ticks = 200000000ULL;  // bound of one cross-column wait: 2 s at 100 MHz
   // FP32 smoothing blocks (precision 1), per level: working copy g, its
   // start g0, effective right-hand side r32, FP64 defect d64
   std::vector<float *> g32, g0_32, r32;
@@ -177,11 +178,11 @@ int queue_sweeps(nrxx_ctx *c, int level, Real *st, const Real *rhs, const std::v
     const int grid = std::max(1, std::min(full, nsw * A.nx));
     if constexpr (sizeof(Real) == 8)
       CHK(launch_bsweep(c->M, A.order, c->qnw, grid, c->qtab[level], c->qunits[level], A.nx, nsw,
-                        bits, c->qcnt[level], A.nx, c->qactive, c->derr, c->dabort, 200000000ULL,
+                        bits, c->qcnt[level], A.nx, c->qactive, c->derr, c->dabort, c->wait_ticks,
                         c->stream, st, rhs));
     else
       CHK(launch_bsweep32(c->M, A.order, c->qnw, grid, c->qtab[level], c->qunits[level], A.nx, nsw,
-                          bits, c->qcnt[level], A.nx, c->qactive, c->derr, c->dabort, 200000000ULL,
+                          bits, c->qcnt[level], A.nx, c->qactive, c->derr, c->dabort, c->wait_ticks,
                           c->stream, st, rhs));
     *launches += 1.0;
   }
@@ -215,7 +216,7 @@ int sweep_impl(nrxx_ctx *c, int level, double *st, const double *rhs, int mask, 
         c->pbase[level] = 0;
       }
       CHK(launch_sweep_persist(c->M, A, st, rhs, nsw, bits, c->cnt[level], (int)c->pbase[level],
-                               c->derr, c->dabort, 200000000ULL /* 2 s */, c->stream));
+                               c->derr, c->dabort, c->wait_ticks, c->stream));
       c->pbase[level] += (long long)nsw * A.ny;
       launches += 1.0;
     }
@@ -291,7 +292,7 @@ int sweep32_impl(nrxx_ctx *c, int level, double *st, const double *rhs, int mask
         c->pbase[level] = 0;
       }
       CHK(launch_sweep_persist32(c->M, A, g, r, nsw, bits, c->cnt[level], (int)c->pbase[level],
-                                 c->derr, c->dabort, 200000000ULL, c->stream));
+                                 c->derr, c->dabort, c->wait_ticks, c->stream));
       c->pbase[level] += (long long)nsw * A.ny;
       launches += 1.0;
     }
@@ -717,6 +718,13 @@ int nrxx_solve(nrxx_ctx *c, double *state, double tol, int max_cycles, double re
     if (hist_out) hist_out[n] = nrm;
   }
   return nrm <= tol * ref_norm ? NRXX_OK : NRXX_EMAXIT;
+}
+
+int nrxx_set_wait_limit(nrxx_ctx *c, double seconds) {
+  if (!c) return NRXX_EINVAL;
+  if (!(seconds >= 1e-8) || seconds > 3600.0) return fail(c, NRXX_EINVAL, "wait limit %g s", seconds);
+  c->wait_ticks = (unsigned long long)(seconds * 1e8);
+  return NRXX_OK;
 }
 
 int nrxx_sweep_stats(nrxx_ctx *c, double *ms_out, double *cells_out, double *launches_out,

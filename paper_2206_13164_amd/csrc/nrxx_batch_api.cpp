@@ -51,12 +51,12 @@ struct nrxx_batch {
   std::vector<double *> cur;    // level-0 state pointers in the tables
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double ms = 0.0, cells = 0.0;
+  unsigned long long wait_ticks = 200000000ULL;  // bound of one cross-column wait: 2 s at 100 MHz
 };
 
 namespace {
 
 thread_local std::string g_batch_create_error;
-constexpr unsigned long long kWaitLimit = 200000000ULL;  // 2 s of the 100 MHz clock
 
 int bfail(nrxx_batch *b, int code, const char *fmt, ...) {
   char buf[512];
@@ -150,7 +150,7 @@ int smooth(nrxx_batch *b, Group &G, int k, int nsteps, int which) {
     BCHK(launch_bfill(G.cnt[k], G.cntsize[k], 0, G.stream));
     const int grid = std::max(1, std::min(G.grid, nsw * U));
     BCHK(launch_bsweep(G.M, G.order, G.nw, grid, G.dtab[k], G.units[G.major][which][k], U, nsw,
-                       dirs, G.cnt[k], G.cols[k], b->active, b->derr, b->dabort, kWaitLimit,
+                       dirs, G.cnt[k], G.cols[k], b->active, b->derr, b->dabort, b->wait_ticks,
                        G.stream));
   }
   return NRXX_OK;
@@ -661,6 +661,14 @@ int nrxx_batch_autotune(nrxx_batch *b, double *const *states) {
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
+  return NRXX_OK;
+}
+
+int nrxx_batch_set_wait_limit(nrxx_batch *b, double seconds) {
+  if (!b) return NRXX_EINVAL;
+  if (!(seconds >= 1e-8) || seconds > 3600.0) return bfail(b, NRXX_EINVAL, "wait limit %g s", seconds);
+  b->wait_ticks = (unsigned long long)(seconds * 1e8);
+  for (auto &G : b->g) drop_graph(G);  // captured cycles hold the old limit
   return NRXX_OK;
 }
 

@@ -77,6 +77,8 @@ EXPORTS = {
     "nrxx_batch_vcycle": (c_int, [c_void_p, _PP, c_void_p]),
     "nrxx_batch_solve": (c_int, [c_void_p, _PP, c_double, c_int, c_int, c_void_p, c_void_p, c_void_p]),
     "nrxx_batch_stats": (c_int, [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double), c_int]),
+    "nrxx_set_wait_limit": (c_int, [c_void_p, c_double]),
+    "nrxx_batch_set_wait_limit": (c_int, [c_void_p, c_double]),
     "nrxx_init_fields": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int]),
     "nrxx_state_fields": (c_int, [c_void_p, c_int, c_void_p, c_void_p]),
     "nrxx_mlp_create": (c_int, [c_void_p, c_int, c_int, c_void_p, ctypes.POINTER(c_void_p)]),
@@ -256,6 +258,9 @@ class Context:
         self._chk(load().nrxx_state_fields(self.h, level, _ptr(state), _ptr(out)))
         return out
 
+    def set_wait_limit(self, seconds):
+        self._chk(load().nrxx_set_wait_limit(self.h, float(seconds)))
+
     def sweep_stats(self, reset=False):
         """(device ms in sweep kernels, cell updates, sweep kernel launches)."""
         ms, cells, launches = c_double(), c_double(), c_double()
@@ -356,6 +361,9 @@ class Batch:
                                      ref.ctypes.data_as(c_void_p))
         self._chk(rc, allow=(NRXX_EMAXIT,))
         return rc, cyc, nrm, ref
+
+    def set_wait_limit(self, seconds):
+        self._chk(load().nrxx_batch_set_wait_limit(self.h, float(seconds)))
 
     def stats(self, reset=False):
         ms, cells = c_double(), c_double()

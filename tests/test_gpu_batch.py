@@ -153,3 +153,22 @@ def test_batch_autotune_restores_states_and_keeps_results():
     b.sweep(st, nsteps=1)
     for k in range(len(specs)):
         assert bool((st[k] == want[k]).all()), k
+
+
+def test_batch_wait_timeout_is_reported_and_the_batch_recovers():
+    require_gpu()
+    from paper_2206_13164_amd import nrxx as N
+    specs = mixed_specs()
+    b = N.Batch(specs)
+    st0 = random_states(b, specs, 61)
+    st = [x.clone() for x in st0]
+    b.set_wait_limit(1e-8)
+    with pytest.raises(N.NrxxError) as ei:
+        b.sweep(st, nsteps=2)
+    assert ei.value.code == N.NRXX_EHIP
+    b.set_wait_limit(2.0)
+    st = [x.clone() for x in st0]
+    b.sweep(st, nsteps=2)
+    want = single_results(specs, st0, lambda c, d: c.sweep(d, nsteps=2))
+    for k in range(len(specs)):
+        assert bool((st[k] == want[k]).all()), k

@@ -316,3 +316,31 @@ def test_persistent_and_diagonal_schedules_agree_bitwise(orc, case):
     got = ctx_p.to_device(st)
     ctx_p.sweep(got, dir_mask=15, nsteps=2)
     assert state_err(ctx_p.to_host(got, st.shape[-1]), want, s["M"]) < TOL_STEP
+
+
+@pytest.mark.parametrize("schedule", [2, 3])
+def test_wait_timeout_is_reported_and_the_context_recovers(schedule):
+    # failure path forced from the host: a 10 ns bound on the cross-column
+    # waits makes the persistent sweep give up (every workgroup exits); the
+    # next synchronising call reports it, and after restoring the bound the
+    # same context sweeps bit for bit like a fresh one
+    require_gpu()
+    from paper_2206_13164_amd import nrxx as N
+    s = I.spec("lid32_bgk_m3", nx=64, ny=64, levels=2, schedule=schedule)
+    st = I.random_state(s, seed=7, amp=0.05)
+    ctx = context(s)
+    d = ctx.to_device(st)
+    ctx.set_wait_limit(1e-8)
+    ctx.sweep(d, nsteps=2)
+    with pytest.raises(N.NrxxError) as ei:
+        ctx.residual(d)
+    assert ei.value.code == N.NRXX_EHIP
+    ctx.set_wait_limit(2.0)
+    d = ctx.to_device(st)
+    ctx.sweep(d, nsteps=2)
+    fresh = context(s)
+    w = fresh.to_device(st)
+    fresh.sweep(w, nsteps=2)
+    assert bool((d == w).all())
+    with pytest.raises(N.NrxxError):
+        ctx.set_wait_limit(0.0)
