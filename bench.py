@@ -58,11 +58,17 @@ def cycle_accounting(spec):
 
 
 def kernel_source_hash() -> str:
-    """sha256 over the sources of the sweep kernels."""
+    """sha256 over the code of the sweep kernels' sources (comments and
+    whitespace removed, so that editing a comment does not invalidate a
+    committed counter summary)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SRCS:
-        h.update(open(f, "rb").read())
+        text = open(f).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 
@@ -198,7 +204,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver's "
-              "multi-GPU decomposition is a design in DESIGN.md, not part of this build.",
+              "multi-GPU decomposition is a design, not implemented.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -258,7 +258,7 @@ __device__ __forceinline__ void store_record(Real *__restrict__ rec, Real u1, Re
 // ---------------------------------------------------------------------------
 
 // Taylor coefficients of exp(-du t - dth t^2 / 2): the 1-D factors of the
-// exact re-expansion F_M^[u,th] -> F_M^[u+du, th+dth] (Sec. Real(2.3)).
+// exact re-expansion F_M^[u,th] -> F_M^[u+du, th+dth] (Sec. 2.3).
 template <typename Real, int M>
 __device__ __forceinline__ void tcoef(Real du, Real dth, Real (&c)[M + 1]) {
   c[0] = Real(1.0);
@@ -394,7 +394,7 @@ __device__ __forceinline__ Real halfI(const Real *K, int k, int l) {
 }
 
 // Outward flux through a diffuse wall in the cell basis (reading of the
-// Maxwell boundary condition of Sec. Real(2.3) / Sec. 4): the leaving half-range
+// Maxwell boundary condition of Sec. 2.3 / Sec. 4): the leaving half-range
 // of the cell distribution plus the entering half of the wall Maxwellian,
 // whose density makes the net mass flux zero.  fc: the cell's coefficients
 // (LDS cube).
@@ -499,7 +499,7 @@ __device__ __forceinline__ Real local_dt(const LevelArgs &A, Real u1, Real u2, R
   return dt;
 }
 
-// Two-step update of Sec. Real(2.4): new (u, th) from the coefficients fs given in
+// Two-step update of Sec. 2.4: new (u, th) from the coefficients fs given in
 // the old basis (eq. (3)), re-expansion, and the exact constraints of
 // eq. (10).  Result left in cube W.bA and in out; false for rho <= 0,
 // th <= 0 or non-finite values.

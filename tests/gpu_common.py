@@ -8,7 +8,7 @@ from paper_2206_13164_amd import inputs as I
 
 # Tolerances (FP64): one application of an operator, sweep, restriction or
 # correction from identical inputs agrees to 1e-12; fields after the same
-# number of V-cycles agree to 1e-10 (spec bounds).
+# number of V-cycles agree to 1e-10 (the parity bounds of this library).
 TOL_STEP = 1e-12
 TOL_CONVERGED = 1e-10
 

@@ -26,7 +26,7 @@ def small(case, **kw):
 @pytest.mark.parametrize("case", CASES)
 def test_global_maxwellian_is_fixed_point(orc, case):
     # global Maxwellian, static walls at the gas temperature, moving nowhere:
-    # R(f) = 0 (a spec invariant), also with a bulk velocity parallel to
+    # R(f) = 0 (an invariant of the method), also with a bulk velocity parallel to
     # walls that move with it
     s = small(case, wall_theta=[1.3] * 4)
     P = orc.problem(s)
