@@ -236,6 +236,9 @@ typedef struct {
   int32_t grid;          /* persistent sweep workgroups (>= 1) */
   int32_t unit_order;    /* 0: units ordered by column position, then problem;
                             1: by problem (largest first), then column position */
+  int32_t split;         /* 1: each cell team evaluates its own-column terms before the waits
+                            on neighbouring columns (shorter latency); 0: waits first, then an
+                            unsplit team (fewer registers, more teams per CU) */
   double block_ms;       /* last autotune: time of one s1-step block on level 0 */
 } nrxx_batch_tuning;
 
@@ -250,7 +253,7 @@ int nrxx_batch_groups(const nrxx_batch *b);
 int nrxx_batch_get_tuning(const nrxx_batch *b, int group, nrxx_batch_tuning *out);
 /* Sets team_width, grid and unit_order of a group (NRXX_EINVAL if invalid). */
 int nrxx_batch_set_tuning(nrxx_batch *b, int group, const nrxx_batch_tuning *t);
-/* Times every candidate (team width x grid {all resident, half} x unit order)
+/* Times every candidate (split x team width x grid {all resident, half} x unit order)
  * on one s1-step smoothing block of the finest level of `states`, keeps the
  * fastest per group, and restores `states` bit for bit. */
 int nrxx_batch_autotune(nrxx_batch *b, double *const *states);

@@ -177,7 +177,7 @@ int queue_sweeps(nrxx_ctx *c, int level, Real *st, const Real *rhs, const std::v
     const int full = sizeof(Real) == 8 ? c->qgrid : c->qgrid32;
     const int grid = std::max(1, std::min(full, nsw * A.nx));
     if constexpr (sizeof(Real) == 8)
-      CHK(launch_bsweep(c->M, A.order, c->qnw, grid, c->qtab[level], c->qunits[level], A.nx, nsw,
+      CHK(launch_bsweep(c->M, A.order, c->qnw, 1, grid, c->qtab[level], c->qunits[level], A.nx, nsw,
                         bits, c->qcnt[level], A.nx, c->qactive, c->derr, c->dabort, c->wait_ticks,
                         c->stream, st, rhs));
     else
@@ -513,7 +513,7 @@ int nrxx_create(const nrxx_problem *p, void *hip_stream, nrxx_ctx **out) {
   // all resident at once; 2) or one launch per anti-diagonal (1)
   if (P.schedule == 0 || P.schedule == 3) {
     c->qnw = P.M <= 5 ? 8 : 2;
-    c->qgrid = bsweep_resident(P.M, P.order, c->qnw);
+    c->qgrid = bsweep_resident(P.M, P.order, c->qnw, 1);
     c->qgrid32 = P.precision == 1 ? bsweep_resident32(P.M, P.order, c->qnw) : 1;
     bool qok = c->qgrid >= 1 && c->qgrid32 >= 1 &&
                hipMalloc((void **)&c->qactive, sizeof(int)) == hipSuccess;

@@ -60,8 +60,11 @@ __device__ __forceinline__ void stage_args(const LevelArgs &src, LevelArgs &dst)
 // its own column), the others between the two halves of the cell team.
 // With st_ovr non-null (one problem, the single-problem library), its state
 // and right-hand side replace the table's pointers; this is also how FP32
-// records (Real = float) are swept.
-template <typename Real, int M, int ORDER, int NW>
+// records (Real = float) are swept.  SPLIT = false takes all waits of a cell
+// (one acquire) before an unsplit cell team: longer per-cell latency, but a
+// much smaller register footprint, so more teams fit on a CU -- the better
+// trade when many problems supply independent columns.
+template <typename Real, int M, int ORDER, int NW, bool SPLIT>
 __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__ tab,
                                                       const int *__restrict__ units, int U,
                                                       int nsweep, unsigned dirs, int *queue,
@@ -104,6 +107,35 @@ __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__
     int known = 0;  // rows of the own column known finished in sweep s-1 (thread 0)
     for (int b = 0; b < ny; ++b) {
       const int j = jrev ? ny - 1 - b : b;
+      if (!SPLIT) {
+        if (threadIdx.x == 0) {
+          bool ok = true;
+          if (s > 0) {
+            const int need = pjrev ? ny - (j - 2 > 0 ? j - 2 : 0) : (j + 2 < ny - 1 ? j + 2 : ny - 1) + 1;
+            ok = wait_at_least(cp + i, need, abort_flag, limit);
+            const int bp = pjrev ? ny - 1 - j : j;
+            for (int d = -2; d <= 2 && ok; ++d) {
+              const int ii = i + d;
+              if (d == 0 || ii < 0 || ii >= nx) continue;
+              ok = wait_at_least(cp + ii, bp + 1, abort_flag, limit);
+            }
+          }
+          if (ok && p > 0) ok = wait_at_least(cs + prev, b + 1, abort_flag, limit);
+          if (ok) acquire_agent();
+          sc[L::SAB] = ok ? Real(0.0) : Real(1.0);
+        }
+        __syncthreads();
+        if (sc[L::SAB] != Real(0.0)) {
+          if (threadIdx.x == 0) atomicOr(err, 4);
+          return;  // uniform across the team
+        }
+        cell_team<Real, M, ORDER, NW, MODE_SWEEP>(sA, lds, st, rhs, nullptr, nullptr, nullptr, i, j,
+                                                  err);
+        if (threadIdx.x == 0)
+          __hip_atomic_store(cs + i, b + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        continue;
+      }
       if (s > 0) {
         if (threadIdx.x == 0) {
           const int need = pjrev ? ny - (j - 2 > 0 ? j - 2 : 0) : (j + 2 < ny - 1 ? j + 2 : ny - 1) + 1;
@@ -290,8 +322,16 @@ bool batch_width_ok(int M, int nw) {
 int batch_default_width(int M) { return M <= 5 ? 8 : 4; }
 
 #define NRXX_BSWEEP(MM, OO, NWV)                                                                   \
-  hipLaunchKernelGGL((k_bsweep<Real, MM, OO, NWV>), dim3(grid), dim3(NWV * WAVE), 0, s, tab, units, \
-                     U, nsweep, dirs, queue, cstride, active, err, abort_flag, limit, st_ovr, rhs_ovr)
+  do {                                                                                             \
+    if (split)                                                                                     \
+      hipLaunchKernelGGL((k_bsweep<Real, MM, OO, NWV, true>), dim3(grid), dim3(NWV * WAVE), 0, s,  \
+                         tab, units, U, nsweep, dirs, queue, cstride, active, err, abort_flag,    \
+                         limit, st_ovr, rhs_ovr);                                                  \
+    else if constexpr (sizeof(Real) == 8)                                                          \
+      hipLaunchKernelGGL((k_bsweep<Real, MM, OO, NWV, false>), dim3(grid), dim3(NWV * WAVE), 0, s, \
+                         tab, units, U, nsweep, dirs, queue, cstride, active, err, abort_flag,    \
+                         limit, st_ovr, rhs_ovr);                                                  \
+  } while (0)
 #define NRXX_BSWEEP_W(MM, OO)                   \
   switch (nw) {                                 \
     case 1: NRXX_BSWEEP(MM, OO, 1); break;      \
@@ -308,26 +348,28 @@ struct BigW {
   static constexpr int W = M <= 5 ? 8 : 4;
 };
 
-template <typename Real, int M, int ORDER>
+template <typename Real, int M, int ORDER, bool SP>
 int occupancy_of(int nw, int *per) {
   hipError_t e;
   switch (nw) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_bsweep<Real, M, ORDER, 1>, WAVE, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_bsweep<Real, M, ORDER, 2>, 2 * WAVE, 0); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_bsweep<Real, M, ORDER, 4>, 4 * WAVE, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_bsweep<Real, M, ORDER, 1, SP>, WAVE, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_bsweep<Real, M, ORDER, 2, SP>, 2 * WAVE, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_bsweep<Real, M, ORDER, 4, SP>, 4 * WAVE, 0); break;
     default:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_bsweep<Real, M, ORDER, BigW<M>::W>,
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_bsweep<Real, M, ORDER, BigW<M>::W, SP>,
                                                        BigW<M>::W * WAVE, 0);
   }
   return e == hipSuccess ? 0 : -1;
 }
 
 template <typename Real>
-hipError_t launch_bsweep_t(int M, int order, int nw, int grid, const BLevel *tab, const int *units,
-                           int U, int nsweep, unsigned dirs, int *queue, int cstride,
-                           const int *active, int *err, int *abort_flag, unsigned long long limit,
-                           hipStream_t s, Real *st_ovr, const Real *rhs_ovr) {
-  if (!batch_width_ok(M, nw) || grid < 1) return hipErrorInvalidValue;
+hipError_t launch_bsweep_t(int M, int order, int nw, int split, int grid, const BLevel *tab,
+                           const int *units, int U, int nsweep, unsigned dirs, int *queue,
+                           int cstride, const int *active, int *err, int *abort_flag,
+                           unsigned long long limit, hipStream_t s, Real *st_ovr,
+                           const Real *rhs_ovr) {
+  if (!batch_width_ok(M, nw) || grid < 1 || (!split && sizeof(Real) != 8))
+    return hipErrorInvalidValue;
   NRXX_DISPATCH_M(M, {
     if (order == 1) {
       NRXX_BSWEEP_W(MM, 1);
@@ -338,7 +380,7 @@ hipError_t launch_bsweep_t(int M, int order, int nw, int grid, const BLevel *tab
   return hipGetLastError();
 }
 
-template <typename Real>
+template <typename Real, bool SP>
 int resident_t(int M, int order, int nw) {
   int dev = 0, ncu = 0, per = 0;
   if (!batch_width_ok(M, nw)) return 0;
@@ -347,7 +389,7 @@ int resident_t(int M, int order, int nw) {
   int rc = -1;
   switch (M) {
 #define NRXX_OCC(MM) \
-    case MM: rc = order == 1 ? occupancy_of<Real, MM, 1>(nw, &per) : occupancy_of<Real, MM, 2>(nw, &per); break;
+    case MM: rc = order == 1 ? occupancy_of<Real, MM, 1, SP>(nw, &per) : occupancy_of<Real, MM, 2, SP>(nw, &per); break;
     NRXX_OCC(3) NRXX_OCC(4) NRXX_OCC(5) NRXX_OCC(6) NRXX_OCC(7) NRXX_OCC(8)
 #undef NRXX_OCC
     default: return 0;
@@ -359,24 +401,27 @@ int resident_t(int M, int order, int nw) {
 #undef NRXX_BSWEEP_W
 #undef NRXX_BSWEEP
 
-hipError_t launch_bsweep(int M, int order, int nw, int grid, const BLevel *tab, const int *units,
-                         int U, int nsweep, unsigned dirs, int *queue, int cstride,
-                         const int *active, int *err, int *abort_flag, unsigned long long limit,
-                         hipStream_t s, double *st_ovr, const double *rhs_ovr) {
-  return launch_bsweep_t<double>(M, order, nw, grid, tab, units, U, nsweep, dirs, queue, cstride,
-                                 active, err, abort_flag, limit, s, st_ovr, rhs_ovr);
+hipError_t launch_bsweep(int M, int order, int nw, int split, int grid, const BLevel *tab,
+                         const int *units, int U, int nsweep, unsigned dirs, int *queue,
+                         int cstride, const int *active, int *err, int *abort_flag,
+                         unsigned long long limit, hipStream_t s, double *st_ovr,
+                         const double *rhs_ovr) {
+  return launch_bsweep_t<double>(M, order, nw, split, grid, tab, units, U, nsweep, dirs, queue,
+                                 cstride, active, err, abort_flag, limit, s, st_ovr, rhs_ovr);
 }
 
 hipError_t launch_bsweep32(int M, int order, int nw, int grid, const BLevel *tab, const int *units,
                            int U, int nsweep, unsigned dirs, int *queue, int cstride,
                            const int *active, int *err, int *abort_flag, unsigned long long limit,
                            hipStream_t s, float *st, const float *rhs) {
-  return launch_bsweep_t<float>(M, order, nw, grid, tab, units, U, nsweep, dirs, queue, cstride,
+  return launch_bsweep_t<float>(M, order, nw, 1, grid, tab, units, U, nsweep, dirs, queue, cstride,
                                 active, err, abort_flag, limit, s, st, rhs);
 }
 
-int bsweep_resident(int M, int order, int nw) { return resident_t<double>(M, order, nw); }
-int bsweep_resident32(int M, int order, int nw) { return resident_t<float>(M, order, nw); }
+int bsweep_resident(int M, int order, int nw, int split) {
+  return split ? resident_t<double, true>(M, order, nw) : resident_t<double, false>(M, order, nw);
+}
+int bsweep_resident32(int M, int order, int nw) { return resident_t<float, true>(M, order, nw); }
 
 hipError_t launch_bresidual(int M, int order, int ncell, const BLevel *tab, int nslot,
                             const int *active, int role, double *partial, hipStream_t s) {

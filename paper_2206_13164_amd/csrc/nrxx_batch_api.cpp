@@ -34,7 +34,7 @@ struct nrxx_batch {
     std::vector<int> U[2];                  // units per sweep per level
     double *partial = nullptr;              // level-0 per-cell scalars
     std::vector<void *> owned;
-    int nw = 0, grid = 0, major = 0;
+    int nw = 0, grid = 0, major = 0, split = 1;
     double tuned_ms = 0.0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -149,7 +149,7 @@ int smooth(nrxx_batch *b, Group &G, int k, int nsteps, int which) {
     for (int q = 0; q < nsw; ++q) dirs |= (unsigned)((s0 + q) & 3) << (2 * q);
     BCHK(launch_bfill(G.cnt[k], G.cntsize[k], 0, G.stream));
     const int grid = std::max(1, std::min(G.grid, nsw * U));
-    BCHK(launch_bsweep(G.M, G.order, G.nw, grid, G.dtab[k], G.units[G.major][which][k], U, nsw,
+    BCHK(launch_bsweep(G.M, G.order, G.nw, G.split, grid, G.dtab[k], G.units[G.major][which][k], U, nsw,
                        dirs, G.cnt[k], G.cols[k], b->active, b->derr, b->dabort, b->wait_ticks,
                        G.stream));
   }
@@ -382,7 +382,7 @@ int nrxx_batch_create(const nrxx_problem *probs, int32_t n, void *hip_stream, nr
     if (ok) ok = hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking) == hipSuccess;
     if (ok) ok = hipEventCreateWithFlags(&G.done, hipEventDisableTiming) == hipSuccess;
     G.nw = batch_default_width(G.M);
-    G.grid = bsweep_resident(G.M, G.order, G.nw);
+    G.grid = bsweep_resident(G.M, G.order, G.nw, 1);
     if (G.grid < 1) ok = false;
     G.major = 0;
   }
@@ -449,6 +449,7 @@ int nrxx_batch_get_tuning(const nrxx_batch *b, int group, nrxx_batch_tuning *t) 
   t->team_width = G.nw;
   t->grid = G.grid;
   t->unit_order = G.major;
+  t->split = G.split;
   t->block_ms = G.tuned_ms;
   return NRXX_OK;
 }
@@ -458,12 +459,14 @@ int nrxx_batch_set_tuning(nrxx_batch *b, int group, const nrxx_batch_tuning *t) 
   if (!t || group < 0 || group >= (int)b->g.size()) return bfail(b, NRXX_EINVAL, "bad group");
   Group &G = b->g[group];
   if (!batch_width_ok(G.M, t->team_width)) return bfail(b, NRXX_EINVAL, "team width %d", t->team_width);
-  if (t->grid < 1 || (t->unit_order != 0 && t->unit_order != 1))
-    return bfail(b, NRXX_EINVAL, "bad grid or unit order");
-  if (G.nw != t->team_width || G.grid != t->grid || G.major != t->unit_order) drop_graph(G);
+  if (t->grid < 1 || (t->unit_order != 0 && t->unit_order != 1) || (t->split != 0 && t->split != 1))
+    return bfail(b, NRXX_EINVAL, "bad grid, unit order or split");
+  if (G.nw != t->team_width || G.grid != t->grid || G.major != t->unit_order || G.split != t->split)
+    drop_graph(G);
   G.nw = t->team_width;
   G.grid = t->grid;
   G.major = t->unit_order;
+  G.split = t->split;
   return NRXX_OK;
 }
 
@@ -614,10 +617,11 @@ int nrxx_batch_autotune(nrxx_batch *b, double *const *states) {
     };
     const int widths[4] = {8, 4, 2, 1};
     double best = 1e300;
-    int bw = G.nw, bg = G.grid, bm = G.major;
+    int bw = G.nw, bg = G.grid, bm = G.major, bs = G.split;
+    for (int sp = 1; sp >= 0 && ok; --sp)
     for (int wi = 0; wi < 4 && ok; ++wi) {
       if (!batch_width_ok(G.M, widths[wi])) continue;
-      const int res = bsweep_resident(G.M, G.order, widths[wi]);
+      const int res = bsweep_resident(G.M, G.order, widths[wi], sp);
       if (res < 1) continue;
       const int grids[2] = {res, std::max(1, res / 2)};
       for (int gi = 0; gi < 2 && ok; ++gi)
@@ -625,6 +629,7 @@ int nrxx_batch_autotune(nrxx_batch *b, double *const *states) {
           G.nw = widths[wi];
           G.grid = grids[gi];
           G.major = m;
+          G.split = sp;
           float ms = 0.f;
           for (int rep = 0; rep < 2 && ok; ++rep) {  // the first run loads the code object
             ok = restore();
@@ -645,6 +650,7 @@ int nrxx_batch_autotune(nrxx_batch *b, double *const *states) {
             bw = G.nw;
             bg = G.grid;
             bm = G.major;
+            bs = G.split;
           }
         }
     }
@@ -652,10 +658,10 @@ int nrxx_batch_autotune(nrxx_batch *b, double *const *states) {
     for (double *p : bak)
       if (p) (void)hipFree(p);
     if (!ok) return bfail(b, NRXX_EHIP, "autotune: copy or allocation failed");
-    if (bw != G.nw || bg != G.grid || bm != G.major) drop_graph(G);
     G.nw = bw;
     G.grid = bg;
     G.major = bm;
+    G.split = bs;
     G.tuned_ms = best;
     drop_graph(G);
   }

@@ -107,15 +107,18 @@ int batch_default_width(int M);
 // st_ovr / rhs_ovr (non-null: a one-problem table) replace the table's
 // state and right-hand side; launch_bsweep32 sweeps FP32 records that way.
 constexpr int kMaxSweepsPerLaunch = 8;
-hipError_t launch_bsweep(int M, int order, int nw, int grid, const BLevel *tab, const int *units,
-                         int U, int nsweep, unsigned dirs, int *queue, int cstride,
-                         const int *active, int *err, int *abort_flag, unsigned long long limit,
-                         hipStream_t s, double *st_ovr = nullptr, const double *rhs_ovr = nullptr);
+// split = 1: cell team split around the cross-column waits (shorter latency);
+// 0: all waits first, unsplit team (fewer registers, more teams per CU).
+hipError_t launch_bsweep(int M, int order, int nw, int split, int grid, const BLevel *tab,
+                         const int *units, int U, int nsweep, unsigned dirs, int *queue,
+                         int cstride, const int *active, int *err, int *abort_flag,
+                         unsigned long long limit, hipStream_t s, double *st_ovr = nullptr,
+                         const double *rhs_ovr = nullptr);
 hipError_t launch_bsweep32(int M, int order, int nw, int grid, const BLevel *tab, const int *units,
                            int U, int nsweep, unsigned dirs, int *queue, int cstride,
                            const int *active, int *err, int *abort_flag, unsigned long long limit,
                            hipStream_t s, float *st, const float *rhs);
-int bsweep_resident(int M, int order, int nw);
+int bsweep_resident(int M, int order, int nw, int split);
 int bsweep_resident32(int M, int order, int nw);
 // role 0: Rbar = rhs - R(st); 1: rhs = R(fbar) + RH; 2: partial = weighted squares
 hipError_t launch_bresidual(int M, int order, int ncell, const BLevel *tab, int nslot,

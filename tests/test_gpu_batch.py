@@ -59,16 +59,17 @@ def test_batch_sweep_bitwise_equals_single_problem_sweeps():
         t = b.tuning(g)
         assert t["team_width"] in (1, 2, 4, 8) and t["grid"] >= 1
     full = [b.tuning(g)["grid"] for g in range(b.groups())]
-    for width in (8, 4, 2, 1):
-        for grid in (None, 3):
-            for order in (0, 1):
-                for g in range(b.groups()):
-                    w = 4 if (width == 8 and b.tuning(g)["M"] > 5) else width
-                    b.set_tuning(g, w, grid or full[g], order)
-                st = [x.clone() for x in st0]
-                b.sweep(st, nsteps=2)
-                for k in range(len(specs)):
-                    assert bool((st[k] == want[k]).all()), (k, width_choice, grid, order)
+    for split in (1, 0):
+        for width in (8, 4, 2, 1):
+            for grid in (None, 3):
+                for order in (0, 1):
+                    for g in range(b.groups()):
+                        w = 4 if (width == 8 and b.tuning(g)["M"] > 5) else width
+                        b.set_tuning(g, w, grid or full[g], order, split)
+                    st = [x.clone() for x in st0]
+                    b.sweep(st, nsteps=2)
+                    for k in range(len(specs)):
+                        assert bool((st[k] == want[k]).all()), (k, split, width, grid, order)
 
 
 @pytest.mark.parametrize("levels", [(2, 2, 2, 2, 2), (3, 3, 2, 1, 3)])
