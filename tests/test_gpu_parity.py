@@ -344,3 +344,16 @@ def test_wait_timeout_is_reported_and_the_context_recovers(schedule):
     assert bool((d == w).all())
     with pytest.raises(N.NrxxError):
         ctx.set_wait_limit(0.0)
+
+
+def test_queue_schedule_with_more_columns_than_resident_workgroups():
+    # 640 columns: more than the device holds workgroups of the queue kernel
+    # at once, so columns are taken dynamically; still the serial order
+    require_gpu()
+    s = small_spec(3, 1, 2, 0, nx=640, ny=16, levels=1)
+    st = I.random_state(s, seed=29, amp=0.05)
+    cq, cd = context(dict(s, schedule=3)), context(dict(s, schedule=1))
+    a, b = cq.to_device(st), cd.to_device(st)
+    cq.sweep(a, nsteps=2)
+    cd.sweep(b, nsteps=2)
+    assert bool((a == b).all())
