@@ -138,14 +138,15 @@ __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__
       }
       if (s > 0) {
         if (threadIdx.x == 0) {
+          // rows j - 2 .. j + 2 of the own column
           const int need = pjrev ? ny - (j - 2 > 0 ? j - 2 : 0) : (j + 2 < ny - 1 ? j + 2 : ny - 1) + 1;
           bool ok = true;
           if (known < need) {
-            ok = wait_at_least(cp + i, need, abort_flag, limit);
+            int seen = need;
+            ok = wait_at_least(cp + i, need, abort_flag, limit, &seen);
             if (ok) {
               acquire_agent();
-              known = __hip_atomic_load(cp + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              if (known < need) known = need;
+              known = seen;
             }
           }
           sc[L::SAB] = ok ? Real(0.0) : Real(1.0);

@@ -366,38 +366,76 @@ __device__ __forceinline__ Real limited(int limiter, Real hi, Real c, Real lo) {
   return limiter == 1 ? Real(0.5) * (hi - lo) : minmod<Real>(hi - c, c - lo);
 }
 
-// Probabilists' Hermite polynomial by recurrence.
-template <typename Real>
+// Probabilists' Hermite polynomial He_n(x), 0 <= n <= NMAX, by recurrence;
+// the recurrence runs to NMAX for every n (unrolled, no lane-dependent trip
+// count) and keeps step n.
+template <typename Real, int NMAX>
 __device__ __forceinline__ Real hermite(int n, Real x) {
   Real h0 = Real(1.0), h1 = x;
-  if (n == 0) return Real(1.0);
-  for (int k = 1; k < n; ++k) {
-    Real h2 = x * h1 - k * h0;
+  Real hn = n == 0 ? Real(1.0) : x;
+#pragma unroll
+  for (int k = 1; k < NMAX; ++k) {
+    const Real h2 = x * h1 - Real(k) * h0;
     h0 = h1;
     h1 = h2;
+    if (k + 1 == n) hn = h1;
   }
-  return h1;
+  return hn;
 }
 
 // I_kl(a) = (2 pi)^-1/2 int_{-a}^inf He_k He_l e^{-w^2/2} dw from the
 // half-range moments K_n (in LDS) and He_k He_l = sum_j k! l! / (j! (k-j)!
-// (l-j)!) He_{k+l-2j}.
+// (l-j)!) He_{k+l-2j}.  The integer coefficient is carried as a running
+// product, c_j = c_{j-1} (k-j+1) (l-j+1) / j (every step divides exactly;
+// below 2^24 for the k <= M, l <= M + 1 used here), so the loop reads no
+// table from global memory, whose cached lines the acquires of the sweep
+// kernels keep invalidating.  (Unrolling this loop spills registers in the
+// sweep kernels.)
 template <typename Real>
 __device__ __forceinline__ Real halfI(const Real *K, int k, int l) {
   if (l < 0) return Real(0.0);
-  Real acc = Real(0.0);
-  int jm = k < l ? k : l;
-  for (int j = 0; j <= jm; ++j)
-    acc += Real(c_fact.v[k]) * Real(c_fact.v[l]) * (Real(c_fact.inv[j]) * Real(c_fact.inv[k - j]) * Real(c_fact.inv[l - j])) *
-           K[k + l - 2 * j];
+  const int jm = k < l ? k : l;
+  Real acc = K[k + l];
+  int cf = 1;
+  for (int j = 1; j <= jm; ++j) {
+    cf = cf * (k - j + 1) * (l - j + 1) / j;
+    acc += Real(cf) * K[k + l - 2 * j];
+  }
   return acc;
+}
+
+// Half-range tables of a diffuse wall: K_n(a), n <= 2M+1, and J+_kl(a),
+// k, l <= M, in the wavefront's misc scratch.  They depend on the cell only
+// through a = sig u_d / sqrt(th), so a cell team can build them before it
+// has the cell's coefficients in LDS; wall_flux then reads them.
+template <typename Real, int M>
+__device__ void wall_tables(int wall, Real u1, Real u2, Real th, Wave<Real, M> &W) {
+  using g = G<M>;
+  const int lane = W.lane;
+  const int d = (wall == 0 || wall == 2) ? 1 : 0;
+  const Real sig = (wall == 1 || wall == 2) ? Real(1.0) : -Real(1.0);
+  const Real a = sig * (d == 0 ? u1 : u2) / sqrt(th);
+  Real *K = W.misc + g::KOFF;
+  Real *Jp = W.misc + g::JOFF;
+  // K_n(a) = (2 pi)^-1/2 int_{-a}^inf He_n e^{-w^2/2}
+  const Real ga = exp(-Real(0.5) * a * a) * (Real(0.5) * Real(M_2_SQRTPI) * Real(M_SQRT1_2));
+  for (int n = lane; n <= 2 * M + 1; n += WAVE)
+    K[n] = n == 0 ? Real(0.5) * erfc(-a * Real(M_SQRT1_2)) : hermite<Real, 2 * M>(n - 1, -a) * ga;
+  wsync();
+  // J+_kl(a) = a I_kl + I_{k,l+1} + l I_{k,l-1}
+  for (int t = lane; t < (M + 1) * (M + 1); t += WAVE) {
+    int k = t / (M + 1), l = t % (M + 1);
+    Jp[t] = a * halfI<Real>(K, k, l) + halfI<Real>(K, k, l + 1) + l * halfI<Real>(K, k, l - 1);
+  }
+  wsync();
 }
 
 // Outward flux through a diffuse wall in the cell basis (reading of the
 // Maxwell boundary condition of Sec. 2.3 / Sec. 4): the leaving half-range
 // of the cell distribution plus the entering half of the wall Maxwellian,
 // whose density makes the net mass flux zero.  fc: the cell's coefficients
-// (LDS cube).
+// (LDS cube).  The same wavefront has built the wall's tables (wall_tables)
+// for the same (wall, u1, u2, th).
 template <typename Real, int M>
 __device__ void wall_flux(const LevelArgs &A, int wall, Real u1, Real u2, Real th,
                           const Real *fc, Wave<Real, M> &W, Real (&phi)[G<M>::SL]) {
@@ -407,21 +445,8 @@ __device__ void wall_flux(const LevelArgs &A, int wall, Real u1, Real u2, Real t
   const int d = (wall == 0 || wall == 2) ? 1 : 0;
   const Real sig = (wall == 1 || wall == 2) ? Real(1.0) : -Real(1.0);
   const Real sq = sqrt(th);
-  const Real a = sig * (d == 0 ? u1 : u2) / sq;
-  Real *K = W.misc + g::KOFF;
-  Real *Jp = W.misc + g::JOFF;
+  const Real *Jp = W.misc + g::JOFF;
   Real *bc = W.misc + g::BOFF;
-  // K_n(a) = (2 pi)^-1/2 int_{-a}^inf He_n e^{-w^2/2}
-  for (int n = lane; n <= 2 * M + 1; n += WAVE)
-    K[n] = n == 0 ? Real(0.5) * erfc(-a * Real(M_SQRT1_2))
-                  : hermite<Real>(n - 1, -a) * exp(-Real(0.5) * a * a) * (Real(0.5) * Real(M_2_SQRTPI) * Real(M_SQRT1_2));
-  wsync();
-  // J+_kl(a) = a I_kl + I_{k,l+1} + l I_{k,l-1}
-  for (int t = lane; t < (M + 1) * (M + 1); t += WAVE) {
-    int k = t / (M + 1), l = t % (M + 1);
-    Jp[t] = a * halfI<Real>(K, k, l) + halfI<Real>(K, k, l + 1) + l * halfI<Real>(K, k, l - 1);
-  }
-  wsync();
   // leaving half: sum_{beta_d} f_beta th^{(a_d-b_d)/2} sqrt(th) sig^{a_d+b_d} J+_{a_d b_d} / a_d!
   const Real isq = Real(1.0) / sq;
   const int dst = d == 0 ? 1 : g::D1;
@@ -432,9 +457,12 @@ __device__ void wall_flux(const LevelArgs &A, int wall, Real u1, Real u2, Real t
       int ad = d == 0 ? S.a1[r] : S.a2[r];
       int at = (d == 0 ? S.a2[r] : S.a1[r]) + 2 * S.m[r];  // transverse degree
       int base = S.ca[r] - ad * dst;                      // alpha with alpha_d = 0
-      Real pa = Real(1.0);
-      for (int q = 0; q < ad; ++q) pa *= sq;
-      const Real ifa = Real(c_fact.inv[ad]);
+      Real pa = Real(1.0), fa = Real(1.0);
+      for (int q = 0; q < ad; ++q) {
+        pa *= sq;
+        fa *= Real(q + 1);
+      }
+      const Real ifa = Real(1.0) / fa;  // 1 / a_d!, exact factorial, one rounding
       Real ib = Real(1.0);
 #pragma unroll
       for (int bd = 0; bd <= M; ++bd) {
@@ -618,14 +646,30 @@ __device__ bool cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
   // (one copy of the item code keeps register use low for the many-cell
   // kernels).  Split, pass 0 spreads the y items 2, 3, 6, 7 over wavefronts
   // 0, 1, 2, 3 (mod NW) and pass 1 the x items 0, 1, 4, 5 over wavefronts
-  // NW-1, NW-2, ... (mod NW), unrolled.
+  // NW-1, NW-2, ... (mod NW), unrolled.  An own x item on a wall face (E of
+  // the last column, W of the first) reads nothing but the cell itself, so it
+  // moves to pass 0, on a wavefront that has no y item there when NW = 8:
+  // the wall flux is the longest item, and in pass 1 it would sit on the
+  // critical path of every wall cell -- and the wall column paces the whole
+  // sweep.  Each item still runs the same code, so results do not change.
+  // Only for M <= 5: at larger M the second inlined copy of the item code
+  // spills registers.
+  constexpr bool MOVE = SPLIT && M <= 5;
+  constexpr int wE = NW >= 8 ? 4 : (NW >= 4 ? 2 : 0);  // wavefront of a moved E wall item
+  constexpr int wW = NW >= 8 ? 5 : (NW >= 4 ? 3 : 0);  // and of a moved W wall item
   auto for_items = [&](int pass, auto &&body) {
     if constexpr (SPLIT) {
+      const bool wallE = MOVE && i == nx - 1, wallW = MOVE && i == 0;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int w = pass == 0 ? t % NW : (NW - 1 - t % NW + NW) % NW;
         if (w != wv) continue;
+        if (pass == 1 && ((t == 0 && wallE) || (t == 1 && wallW))) continue;
         body(pass == 0 ? (t < 2 ? 2 + t : 4 + t) : (t < 2 ? t : 2 + t));
+      }
+      if (MOVE && pass == 0) {
+        if (wallE && wv == wE) body(0);
+        if (wallW && wv == wW) body(1);
       }
     } else {
 #pragma unroll 1
@@ -633,6 +677,11 @@ __device__ bool cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
     }
   };
 
+  // With NW >= 4 no wavefront holds two own items (the only ones that can
+  // sit on a wall), so a wall's half-range tables are built here, in the
+  // face-state stage, while the other wavefronts form their face states,
+  // and stay in the wavefront's scratch until its flux stage.
+  constexpr bool EARLY_TABLES = NW >= 4;
   auto face_states = [&](int pass) {
   for_items(pass, [&](const int q) {
     const int f = q & 3, s = q >> 2, D = face_dir(f);
@@ -643,6 +692,7 @@ __device__ bool cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
     Cell<Real, M> X;
     if (s == 0) {
       const bool flat = ORDER == 1 || k == 0 || k == n - 1;
+      if (EARLY_TABLES && wall) wall_tables<Real, M>(face_wall(f), c.u1, c.u2, c.th, W);
       if (flat) X = c;
       else {
         Cell<Real, M> hi, lo;
@@ -685,6 +735,7 @@ __device__ bool cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
     Real T[g::SL];
     if (wall) {
       if (s == 1) return;
+      if (!EARLY_TABLES) wall_tables<Real, M>(face_wall(f), c.u1, c.u2, c.th, W);
       wall_flux<Real, M>(A, face_wall(f), c.u1, c.u2, c.th, bC, W, T);
       put_slots<Real, M>(lds + L::T + q * g::SLOT, lane, T);
       return;
@@ -921,14 +972,24 @@ struct TeamWidth {
 // records every other team on the XCD is working on.  The caller issues one
 // agent-scope acquire fence (acquire_agent) after all waits of a cell have
 // succeeded.  Bounded: gives up after `limit` ticks of the 100 MHz wall clock
-// or when another team has aborted; returns false then.
+// or when another team has aborted; returns false then.  *seen (optional)
+// receives the value that satisfied the wait: a fence after the wait makes
+// the writes released up to that value visible, and no later ones.
 __device__ __forceinline__ bool wait_at_least(const int *flag, int target, int *abort_flag,
-                                              unsigned long long limit) {
-  if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) return true;
+                                              unsigned long long limit, int *seen = nullptr) {
+  int v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (v >= target) {
+    if (seen) *seen = v;
+    return true;
+  }
   const unsigned long long t0 = wall_clock64();
   for (;;) {
     __builtin_amdgcn_s_sleep(2);
-    if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) return true;
+    v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (v >= target) {
+      if (seen) *seen = v;
+      return true;
+    }
     if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
     if (wall_clock64() - t0 > limit) {
       __hip_atomic_fetch_or(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
