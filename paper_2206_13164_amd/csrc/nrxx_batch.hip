@@ -78,6 +78,12 @@ __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__
   __shared__ LevelArgs sA;
   Real *sc = lds + L::S;
   const int total = nsweep * U;
+  // the lane's slot map, read from the constant tables once: inside the
+  // loops every cell would re-read them from memory after its acquire (kept
+  // in registers only at one slot per lane; more spill)
+  constexpr bool HOIST_SLOTS = G<M>::SL == 1;
+  Slots<M> slots;
+  slots.init(threadIdx.x % WAVE);
   for (;;) {
     if (threadIdx.x == 0) {
       int u = atomicAdd(queue, 1);
@@ -130,7 +136,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__
           return;  // uniform across the team
         }
         cell_team<Real, M, ORDER, NW, MODE_SWEEP>(sA, lds, st, rhs, nullptr, nullptr, nullptr, i, j,
-                                                  err);
+                                                  err, NoWait(), HOIST_SLOTS ? &slots : nullptr);
         if (threadIdx.x == 0)
           __hip_atomic_store(cs + i, b + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
@@ -172,7 +178,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__
         return ok;
       };
       if (!cell_team<Real, M, ORDER, NW, MODE_SWEEP, true>(sA, lds, st, rhs, nullptr, nullptr,
-                                                           nullptr, i, j, err, wait)) {
+                                                           nullptr, i, j, err, wait, HOIST_SLOTS ? &slots : nullptr)) {
         if (threadIdx.x == 0) atomicOr(err, 4);
         return;  // uniform across the team
       }

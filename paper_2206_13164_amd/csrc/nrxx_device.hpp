@@ -183,13 +183,16 @@ struct Wave {
   Real *bX, *bA, *bB, *misc;
   int lane;
   Slots<M> S;
-  __device__ __forceinline__ void init(Real *base, int ln) {
+  // pre: the lane's slot map built once by the caller (a kernel that loops
+  // over cells passes it, so the table reads stay out of its loop), or null
+  __device__ __forceinline__ void init(Real *base, int ln, const Slots<M> *pre = nullptr) {
     bX = base;
     bA = base + g::CUBE;
     bB = base + 2 * g::CUBE;
     misc = base + 3 * g::CUBE;
     lane = ln;
-    S.init(ln);
+    if (pre) S = *pre;
+    else S.init(ln);
   }
 };
 
@@ -611,12 +614,12 @@ template <typename Real, int M, int ORDER, int NW, int MODE, bool SPLIT = false,
 __device__ bool cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
                           const Real *__restrict__ rhs, const Real *__restrict__ Radd,
                           Real *__restrict__ out, Real *__restrict__ norm_part, int i, int j,
-                          int *err, Wait wait = Wait()) {
+                          int *err, Wait wait = Wait(), const Slots<M> *slots = nullptr) {
   using g = G<M>;
   using L = Lay<M, NW>;
   const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
   Wave<Real, M> W;
-  W.init(lds + L::W + wv * L::WSZ, lane);
+  W.init(lds + L::W + wv * L::WSZ, lane, slots);
   const Slots<M> &S = W.S;
   Real *bC = lds + L::C;
   Real *sc = lds + L::S;

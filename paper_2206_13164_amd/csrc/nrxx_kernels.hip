@@ -49,6 +49,11 @@ __global__ __launch_bounds__(NW * WAVE) void k_sweep_persist(
   __shared__ Real lds[L::TOTAL];
   const int i = blockIdx.x;
   const int nx = A.nx, ny = A.ny;
+  // the lane's slot map, read from the constant tables once, outside the
+  // loops (kept in registers only at one slot per lane; more spill)
+  constexpr bool HOIST_SLOTS = G<M>::SL == 1;
+  Slots<M> slots;
+  slots.init(threadIdx.x % WAVE);
   for (int s = 0; s < nsweep; ++s) {
     const int dir = (dirs >> (2 * s)) & 3;
     const bool irev = dir == 1 || dir == 2, jrev = dir == 2 || dir == 3;
@@ -76,7 +81,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_sweep_persist(
         return ok;
       };
       if (!cell_team<Real, M, ORDER, NW, MODE_SWEEP, true>(A, lds, st, rhs, nullptr, nullptr,
-                                                           nullptr, i, j, err, wait)) {
+                                                           nullptr, i, j, err, wait, HOIST_SLOTS ? &slots : nullptr)) {
         if (threadIdx.x == 0) atomicOr(err, 4);
         return;  // uniform across the team
       }
