@@ -155,6 +155,78 @@ def learned_leg(max_cycles):
             "network": {k: v for k, v in ws.meta.items() if k != "loss"}}
 
 
+def baselines_leg(spec, max_cycles):
+    """The paper's comparison of solvers (Sec. 3.1, 3.2) on the first-order
+    version of the workload: the NMG solve to the workload's tolerance, then
+    explicit time marching (forward Euler, global step) and single-level fast
+    sweeping from the same Maxwellian start for the same wall time, each with
+    the relative residual it reaches and its cell-update rate.  Forward Euler
+    with the unlimited central slopes of the second-order workload itself
+    turns non-physical; the steps it survives there are reported too."""
+    import torch
+    from paper_2206_13164_amd import nrxx as N
+    NA = math.comb(spec["M"] + 3, 3)
+    cells = spec["nx"] * spec["ny"]
+    s1 = dict(spec, order=1)
+    ctx = N.Context(s1)
+    st = ctx.empty(0)
+    ctx.init_maxwellian(st)
+    ref = ctx.residual(st)
+    ctx.solve(st, spec["tol"], max_cycles, ref_norm=ref)
+    ctx.init_maxwellian(st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, cyc, hist = ctx.solve(st, spec["tol"], max_cycles, ref_norm=ref)
+    torch.cuda.synchronize()
+    budget = time.perf_counter() - t0
+    out = {"workload": "first-order version of the benchmark cavity", "budget_s": budget,
+           "nmg": {"cycles": cyc, "seconds": budget, "rel_residual": hist[-1] / ref,
+                   "converged": rc == N.NRXX_OK}}
+
+    def march(c, st, step, chunk):
+        c.init_maxwellian(st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < budget:
+            step(st, chunk)
+            n += chunk
+        torch.cuda.synchronize()
+        return n, time.perf_counter() - t0
+
+    ctx.euler(st, nsteps=10)  # load the code objects
+    n, wall = march(ctx, st, lambda x, k: ctx.euler(x, nsteps=k), 200)
+    out["euler"] = {"steps": n, "seconds": wall, "rel_residual": ctx.residual(st) / ref,
+                    "cell_moment_updates_per_s": n * cells * NA / wall}
+    ctx.close()
+    ctx = N.Context(dict(s1, levels=1))
+    st = ctx.empty(0)
+    ctx.init_maxwellian(st)
+    ctx.sweep(st, nsteps=1)
+    def fs_steps(x, k):
+        ctx.sweep(x, nsteps=k)
+        torch.cuda.synchronize()  # sweeps are asynchronous: keep the clock honest
+
+    n, wall = march(ctx, st, fs_steps, 4)
+    out["fast_sweeping_single_level"] = {
+        "steps": n, "seconds": wall, "rel_residual": ctx.residual(st) / ref,
+        "cell_moment_updates_per_s": 4 * n * cells * NA / wall}
+    ctx.close()
+    ctx = N.Context(spec)
+    st = ctx.empty(0)
+    ctx.init_maxwellian(st)
+    n = 0
+    try:
+        while n < 20000:
+            ctx.euler(st, nsteps=100)
+            n += 100
+        out["euler_second_order_central"] = {"steps": n, "non_physical": False}
+    except N.NrxxError:
+        out["euler_second_order_central"] = {"steps_before_non_physical": n, "non_physical": True}
+    ctx.close()
+    return out
+
+
 def batch_leg(n=16, cycles=6):
     """Batched throughput: n drawn cavities (sides 64/96/128, M 3/5/8,
     BGK/Shakhov, Kn log-uniform in [0.01, 1]) in one batch after autotuning,
@@ -193,6 +265,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned warm-start comparison (256x256 held-out cavity)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-throughput leg")
+    ap.add_argument("--no-baselines", action="store_true",
+                    help="skip the explicit-Euler and single-level fast-sweeping comparison")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the FP32-sweep (precision 1) solve of the same workload")
     ap.add_argument("--max-cycles", type=int, default=200)
@@ -311,6 +385,8 @@ def main():
     if not args.no_mixed:
         out["mixed"] = time_variant(dict(spec, precision=1), tol, args.max_cycles, ref, NA)
         out["mixed"]["speedup_vs_plain"] = (wall / args.steps) / out["mixed"]["time_to_residual_s"]
+    if not args.no_baselines:
+        out["baselines"] = baselines_leg(spec, args.max_cycles)
     if not args.no_batch:
         out["batch"] = batch_leg()
     if not args.no_learned:

@@ -178,6 +178,17 @@ int nrxx_correct(nrxx_ctx *ctx, int level_fine, double *fine, const double *coar
 /* Total mass sum_ij rho_ij dx dy of `state` (synchronises). */
 int nrxx_mass(nrxx_ctx *ctx, int level, const double *state, double *mass_out);
 
+/* Explicit time marching, the baseline of Sec. 3.1: `nsteps` forward Euler
+ * steps of eq. (16) on level `level` with r = 0, each with the global time
+ * step of eq. (17) (the smallest local step of eq. (18) over the level, with
+ * the relaxation cap of the problem): every cell is updated from the same old
+ * state, f <- normalise(f + dt R(f)).  `state` (device, the level's records)
+ * is updated in place.  dt_out (host, may be NULL) gets the step of the last
+ * step (0 when nsteps = 0).  Allocates one level-sized scratch buffer on the
+ * first call (owned by the context).  Synchronises; NRXX_ENONPHYS if an
+ * update made a cell non-physical (the state is then partly updated). */
+int nrxx_euler(nrxx_ctx *ctx, int level, double *state, int nsteps, double *dt_out);
+
 /* One NMG iteration NMG_K(f, 0) of Alg. 2 on the finest-level `state`
  * (gamma recursive calls, s1/s2 smoothing, s3 coarsest steps), followed by
  * the mass correction of Sec. 4 when mass0 > 0.  If norm_out != NULL, writes

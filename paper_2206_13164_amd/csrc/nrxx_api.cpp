@@ -98,6 +98,7 @@ struct nrxx_ctx {
   std::vector<float *> g32, g0_32, r32;
   std::vector<double *> d64;
   double *dblk = nullptr;                // per level: block scale, reference defect norm
+  double *ebuf = nullptr;                // forward Euler: -R of a level (finest-level size)
   std::string err;
   struct Timed { hipEvent_t a, b; double cells, launches; };
   std::vector<Timed> timed;
@@ -584,6 +585,7 @@ int nrxx_destroy(nrxx_ctx *c) {
   for (double *p : c->d64)
     if (p) (void)hipFree(p);
   if (c->dblk) (void)hipFree(c->dblk);
+  if (c->ebuf) (void)hipFree(c->ebuf);
   for (auto *v : {&c->qunits, &c->qcnt})
     for (int *p : *v)
       if (p) (void)hipFree(p);
@@ -675,6 +677,31 @@ int nrxx_mass(nrxx_ctx *c, int level, const double *state, double *mass_out) {
   CHK(hipMemcpyAsync(c->hscal + 2, c->dscal + 2, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   CHK(hipStreamSynchronize(c->stream));
   *mass_out = c->hscal[2];
+  return NRXX_OK;
+}
+
+int nrxx_euler(nrxx_ctx *c, int level, double *state, int nsteps, double *dt_out) {
+  if (!c) return NRXX_EINVAL;
+  if (!level_ok(c, level) || !state || nsteps < 0) return fail(c, NRXX_EINVAL, "bad argument");
+  if (!c->ebuf) {
+    const size_t n = (size_t)c->lv[0].nx * c->lv[0].ny * c->stride;
+    if (hipMalloc((void **)&c->ebuf, n * sizeof(double)) != hipSuccess) {
+      c->ebuf = nullptr;
+      return fail(c, NRXX_ENOMEM, "hipMalloc failed");
+    }
+  }
+  const LevelArgs &A = c->lv[level];
+  for (int k = 0; k < nsteps; ++k) {
+    CHK(launch_euler_dt(c->M, A, state, c->dscal + 3, c->stream));
+    CHK(launch_residual(c->M, A, state, nullptr, nullptr, c->ebuf, nullptr, 0, c->stream));
+    CHK(launch_euler_update(c->M, A, state, c->ebuf, c->dscal + 3, c->derr, c->stream));
+  }
+  if (dt_out) {
+    CHK(hipMemcpyAsync(c->hscal + 3, c->dscal + 3, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  }
+  int rc = check_device(c);
+  if (rc) return rc;
+  if (dt_out) *dt_out = nsteps > 0 ? c->hscal[3] : 0.0;
   return NRXX_OK;
 }
 

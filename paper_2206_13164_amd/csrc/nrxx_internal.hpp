@@ -63,6 +63,12 @@ hipError_t launch_block_scale(const LevelArgs &A, const double *part, double tau
 hipError_t launch_residual(int M, const LevelArgs &A, const double *st, const double *rhs,
                            const double *Radd, double *out, double *norm_part, int mode,
                            hipStream_t s);
+// Forward Euler: *dt_out <- the global step (smallest local step of the
+// level); st <- normalise(st - dt d) per cell, d = -R(st) in the cell basis.
+hipError_t launch_euler_dt(int M, const LevelArgs &A, const double *st, double *dt_out,
+                           hipStream_t s);
+hipError_t launch_euler_update(int M, const LevelArgs &A, double *st, const double *d,
+                               const double *dt, int *err, hipStream_t s);
 hipError_t launch_restrict(int M, const LevelArgs &Afine, const double *fine, const double *fineR,
                            double *coarse, double *coarseR, int *err, hipStream_t s);
 hipError_t launch_correct(int M, const LevelArgs &Afine, double *fine, const double *cnew,

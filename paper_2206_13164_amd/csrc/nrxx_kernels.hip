@@ -340,11 +340,81 @@ __global__ void k_mass_scale(int ncell, double *__restrict__ st, const double *_
   }
 }
 
+// Forward Euler (explicit time marching, eq. (16)) with the global step of
+// eq. (17): the smallest local step (eq. (18), with the relaxation cap) over
+// the level's cells.  One workgroup; the minimum does not depend on the
+// reduction order.
+template <int M>
+__global__ __launch_bounds__(1024) void k_euler_dt(LevelArgs A, const double *__restrict__ st,
+                                                   double *__restrict__ dt_out) {
+  using g = G<M>;
+  __shared__ double part[1024];
+  const int ncell = A.nx * A.ny;
+  double m = INFINITY;
+  for (int c = threadIdx.x; c < ncell; c += 1024) {
+    const double *r = st + (size_t)c * g::STRIDE;
+    const double nu = A.beta * sqrt(M_PI / 2.0) * r[3] * pow(r[2], 1.0 - A.omega) / A.Kn;
+    m = fmin(m, local_dt<double>(A, r[0], r[1], r[2], nu));
+  }
+  part[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] = fmin(part[threadIdx.x], part[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *dt_out = part[0];
+}
+
+// The Euler update of every cell from the same old state: f <- normalise(f
+// + dt R(f)) (Sec. 2.4), given d = -R(f) in the cell's basis (the defect
+// with a zero right-hand side).  One wavefront per cell, four per workgroup;
+// a wavefront without a cell returns before any wavefront-level sync.
+template <int M>
+__global__ __launch_bounds__(4 * WAVE) void k_euler_update(LevelArgs A, double *__restrict__ st,
+                                                           const double *__restrict__ d,
+                                                           const double *__restrict__ dt,
+                                                           int *err) {
+  using g = G<M>;
+  constexpr int WSZ = 3 * g::CUBE + g::MISC;
+  __shared__ double lds[4 * WSZ];
+  const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int cell = blockIdx.x * 4 + wv;
+  if (cell >= A.nx * A.ny) return;
+  Wave<double, M> W;
+  W.init(lds + wv * WSZ, lane);
+  Cell<double, M> c, r;
+  load_cell<double, M>(st + (size_t)cell * g::STRIDE, W.S, c);
+  load_cell<double, M>(d + (size_t)cell * g::STRIDE, W.S, r);
+  const double h = *dt;
+  double fs[g::SL];
+#pragma unroll
+  for (int q = 0; q < g::SL; ++q) fs[q] = c.f[q] - h * r.f[q];
+  Cell<double, M> nc;
+  if (normalise<double, M>(c.u1, c.u2, c.th, fs, W, nc))
+    store_record<double, M>(st + (size_t)cell * g::STRIDE, nc.u1, nc.u2, nc.th, W.bA, lane);
+  else if (lane == 0)
+    atomicOr(err, 1);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+
+hipError_t launch_euler_dt(int M, const LevelArgs &A, const double *st, double *dt_out,
+                           hipStream_t s) {
+  NRXX_DISPATCH_M(M, hipLaunchKernelGGL((k_euler_dt<MM>), dim3(1), dim3(1024), 0, s, A, st, dt_out));
+  return hipGetLastError();
+}
+
+hipError_t launch_euler_update(int M, const LevelArgs &A, double *st, const double *d,
+                               const double *dt, int *err, hipStream_t s) {
+  const int blocks = (A.nx * A.ny + 3) / 4;
+  NRXX_DISPATCH_M(M, hipLaunchKernelGGL((k_euler_update<MM>), dim3(blocks), dim3(4 * WAVE), 0, s, A,
+                                        st, d, dt, err));
+  return hipGetLastError();
+}
 
 hipError_t launch_sweep_diag(int M, const LevelArgs &A, double *st, const double *rhs, int dir,
                              int t, int *err, hipStream_t s) {

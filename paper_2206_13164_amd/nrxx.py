@@ -58,6 +58,7 @@ EXPORTS = {
     "nrxx_restrict": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "nrxx_fas_rhs": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     "nrxx_correct": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
+    "nrxx_euler": (c_int, [c_void_p, c_int, c_void_p, c_int, ctypes.POINTER(c_double)]),
     "nrxx_mass": (c_int, [c_void_p, c_int, c_void_p, ctypes.POINTER(c_double)]),
     "nrxx_fas_vcycle": (c_int, [c_void_p, c_void_p, ctypes.POINTER(c_double)]),
     "nrxx_solve": (c_int, [c_void_p, c_void_p, c_double, c_int, c_double, ctypes.POINTER(c_int),
@@ -233,6 +234,13 @@ class Context:
         m = c_double()
         self._chk(load().nrxx_mass(self.h, level, _ptr(state), ctypes.byref(m)))
         return m.value
+
+    def euler(self, state, nsteps=1, level=0):
+        """`nsteps` forward Euler steps with the global time step (the
+        explicit time-marching baseline); returns the last step's dt."""
+        dt = c_double()
+        self._chk(load().nrxx_euler(self.h, level, _ptr(state), nsteps, ctypes.byref(dt)))
+        return dt.value
 
     def fas_vcycle(self, state, want_norm=True):
         nrm = c_double()

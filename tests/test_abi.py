@@ -59,6 +59,7 @@ def test_null_arguments():
     assert L.nrxx_destroy(None) == N.NRXX_OK
     assert L.nrxx_residual(None, 0, None, None, None, None) == N.NRXX_EINVAL
     assert L.nrxx_solve(None, None, 1e-8, 1, 0.0, None, None) == N.NRXX_EINVAL
+    assert L.nrxx_euler(None, 0, None, 1, None) == N.NRXX_EINVAL
 
 
 @pytest.mark.parametrize("bad", [
