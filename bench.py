@@ -227,6 +227,60 @@ def baselines_leg(spec, max_cycles):
     return out
 
 
+def four_sided_leg(max_cycles):
+    """The paper's solver table for the four-sided cavity (Sec. 5.3, 64x64,
+    M = 5, Shakhov, Kn 0.777): iterations and wall time to the relative
+    residual 1e-8 of forward Euler (steps of the global step), single-level
+    fast sweeping (four-direction steps, each followed by the mass
+    correction) and NMG (V-cycles), all from the global Maxwellian.  The
+    paper's CPU figures are quoted beside them as context."""
+    import torch
+    from paper_2206_13164_amd import inputs as I
+    from paper_2206_13164_amd import nrxx as N
+    s = I.spec("four_sided64_shakhov_m5")
+    tol = s["tol"]
+    out = {"workload": "four_sided64_shakhov_m5", "tol": tol,
+           "paper_cpu": {"iterations": {"euler": 4442, "fast_sweeping": 607, "nmg": 17},
+                         "seconds": {"euler": 6031.19, "fast_sweeping": 2068.4, "nmg": 295.75}}}
+
+    def timed_solve(spec):
+        ctx = N.Context(spec)
+        st = ctx.empty(0)
+        ctx.init_maxwellian(st)
+        ref = ctx.residual(st)
+        ctx.solve(st, tol, 2, ref_norm=ref)  # load the code objects
+        ctx.init_maxwellian(st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, cyc, hist = ctx.solve(st, tol, max_cycles, ref_norm=ref)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ctx.close()
+        return {"iterations": cyc, "seconds": wall, "converged": rc == N.NRXX_OK,
+                "rel_residual": hist[-1] / ref}
+
+    out["nmg"] = timed_solve(s)
+    out["fast_sweeping"] = timed_solve(dict(s, levels=1, s3=1))
+    ctx = N.Context(s)
+    st = ctx.empty(0)
+    ctx.init_maxwellian(st)
+    ref = ctx.residual(st)
+    ctx.euler(st, nsteps=2)
+    ctx.init_maxwellian(st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n, r = 0, ref
+    while r > tol * ref and n < 20000:
+        ctx.euler(st, nsteps=1)
+        n += 1
+        r = ctx.residual(st)
+    wall = time.perf_counter() - t0
+    ctx.close()
+    out["euler"] = {"iterations": n, "seconds": wall, "converged": r <= tol * ref,
+                    "rel_residual": r / ref}
+    return out
+
+
 def batch_leg(n=16, cycles=6):
     """Batched throughput: n drawn cavities (sides 64/96/128, M 3/5/8,
     BGK/Shakhov, Kn log-uniform in [0.01, 1]) in one batch after autotuning,
@@ -387,6 +441,7 @@ def main():
         out["mixed"]["speedup_vs_plain"] = (wall / args.steps) / out["mixed"]["time_to_residual_s"]
     if not args.no_baselines:
         out["baselines"] = baselines_leg(spec, args.max_cycles)
+        out["baselines"]["four_sided_64"] = four_sided_leg(args.max_cycles * 5)
     if not args.no_batch:
         out["batch"] = batch_leg()
     if not args.no_learned:

@@ -80,6 +80,28 @@ def test_mirror_equivariance(orc, case):
     assert np.max(np.abs(Rm - _mirror_x(s, R))) < 1e-12
 
 
+def _rot180(s, st):
+    al = I.alpha_list(s["M"])
+    out = st[::-1, ::-1, :].copy()
+    out[..., :2] *= -1
+    out[..., 3:] *= (-1.0) ** (al[:, 0] + al[:, 1])
+    return out
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_rotation_equivariance_four_sided(orc, case):
+    # (x, y) -> (Lx - x, Ly - y) with every wall moving (the four-sided
+    # cavity of Sec. 5.3: u_N = -u_S, u_E = -u_W, opposite walls at equal
+    # temperature): the configuration is its own rotation, so
+    # R(rot f) = rot R(f)
+    s = small(case, wall_u=[-0.21, 0.3, 0.21, -0.3], wall_theta=[1.2, 0.9, 1.2, 0.9])
+    P = orc.problem(s)
+    st = I.random_state(s, seed=9, amp=0.08)
+    R, _ = orc.residual(P, 0, st)
+    Rr, _ = orc.residual(P, 0, _rot180(s, st))
+    assert np.max(np.abs(Rr - _rot180(s, R))) < 1e-12
+
+
 @pytest.mark.parametrize("case", CASES)
 def test_transpose_equivariance(orc, case):
     # x <-> y with Lx != Ly: catches any mix-up of the two directions
