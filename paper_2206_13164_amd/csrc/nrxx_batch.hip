@@ -75,6 +75,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__
   using L = Lay<M, NW>;
   __shared__ Real lds[L::TOTAL];
   __shared__ int su;
+  __shared__ int sknown;  // rows of the own column known finished in sweep s-1
   __shared__ LevelArgs sA;
   Real *sc = lds + L::S;
   const int total = nsweep * U;
@@ -89,6 +90,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__
       int u = atomicAdd(queue, 1);
       if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) u = total;
       su = u;
+      sknown = 0;
     }
     __syncthreads();
     const int u = su;
@@ -110,7 +112,6 @@ __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__
     const int prev = irev ? i + 1 : i - 1;
     const int pdir = s > 0 ? (dirs >> (2 * (s - 1))) & 3 : 0;
     const bool pjrev = pdir == 2 || pdir == 3;
-    int known = 0;  // rows of the own column known finished in sweep s-1 (thread 0)
     for (int b = 0; b < ny; ++b) {
       const int j = jrev ? ny - 1 - b : b;
       if (!SPLIT) {
@@ -143,24 +144,24 @@ __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__
         continue;
       }
       if (s > 0) {
-        if (threadIdx.x == 0) {
-          // rows j - 2 .. j + 2 of the own column
-          const int need = pjrev ? ny - (j - 2 > 0 ? j - 2 : 0) : (j + 2 < ny - 1 ? j + 2 : ny - 1) + 1;
-          bool ok = true;
-          if (known < need) {
-            int seen = need;
-            ok = wait_at_least(cp + i, need, abort_flag, limit, &seen);
-            if (ok) {
-              acquire_agent();
-              known = seen;
-            }
+        // rows j - 2 .. j + 2 of the own column.  sknown changes only after
+        // the barrier below and is read again only after the row's last
+        // barrier, so the test is uniform and a row whose rows are already
+        // known takes no barrier and no acquire.
+        const int need = pjrev ? ny - (j - 2 > 0 ? j - 2 : 0) : (j + 2 < ny - 1 ? j + 2 : ny - 1) + 1;
+        if (sknown < need) {
+          int seen = need;
+          if (threadIdx.x == 0) {
+            const bool ok = wait_at_least(cp + i, need, abort_flag, limit, &seen);
+            if (ok) acquire_agent();
+            sc[L::SAB] = ok ? Real(0.0) : Real(1.0);
           }
-          sc[L::SAB] = ok ? Real(0.0) : Real(1.0);
-        }
-        __syncthreads();
-        if (sc[L::SAB] != Real(0.0)) {
-          if (threadIdx.x == 0) atomicOr(err, 4);
-          return;  // uniform across the team
+          __syncthreads();
+          if (sc[L::SAB] != Real(0.0)) {
+            if (threadIdx.x == 0) atomicOr(err, 4);
+            return;  // uniform across the team
+          }
+          if (threadIdx.x == 0) sknown = seen;
         }
       }
       auto wait = [&]() -> bool {
