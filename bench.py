@@ -156,7 +156,7 @@ def learned_leg(max_cycles):
 
 
 def baselines_leg(spec, max_cycles):
-    """The paper's comparison of solvers (Sec. 3.1, 3.2) on the first-order
+    """The paper's comparison of solvers (Sec. 2.4, 3.1, 3.2) on the first-order
     version of the workload: the NMG solve to the workload's tolerance, then
     explicit time marching (forward Euler, global step) and single-level fast
     sweeping from the same Maxwellian start for the same wall time, each with
@@ -228,7 +228,7 @@ def baselines_leg(spec, max_cycles):
 
 
 def four_sided_leg(max_cycles):
-    """The paper's solver table for the four-sided cavity (Sec. 5.3, 64x64,
+    """The paper's solver table for the four-sided cavity (Sec. 4.2, 64x64,
     M = 5, Shakhov, Kn 0.777): iterations and wall time to the relative
     residual 1e-8 of forward Euler (steps of the global step), single-level
     fast sweeping (four-direction steps, each followed by the mass

@@ -178,7 +178,8 @@ int nrxx_correct(nrxx_ctx *ctx, int level_fine, double *fine, const double *coar
 /* Total mass sum_ij rho_ij dx dy of `state` (synchronises). */
 int nrxx_mass(nrxx_ctx *ctx, int level, const double *state, double *mass_out);
 
-/* Explicit time marching, the baseline of Sec. 3.1: `nsteps` forward Euler
+/* Explicit time marching (Sec. 2.4), the baseline fast sweeping and NMG are
+ * compared with (Sec. 3, 4): `nsteps` forward Euler
  * steps of eq. (16) on level `level` with r = 0, each with the global time
  * step of eq. (17) (the smallest local step of eq. (18) over the level, with
  * the relaxation cap of the problem): every cell is updated from the same old

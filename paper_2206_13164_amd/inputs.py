@@ -59,7 +59,7 @@ WORKLOADS = {
     # coarsest grid
     "paper_table1_32": dict(nx=32, ny=32, M=5, collision=1, Pr=2.0 / 3.0, Kn=0.1, order=1,
                             wall_u=[0.0, 0.0, 0.2097, 0.0], levels=3, tol=1e-8),
-    # four-sided lid-driven cavity with anti-parallel wall motion (Sec. 5.3):
+    # four-sided lid-driven cavity with anti-parallel wall motion (Sec. 4.2):
     # top moves right and the right wall up at U_W (50 m/s at 273 K, 0.2097),
     # bottom and left walls the opposite way; Shakhov, Kn 0.777, M = 5, 1st
     # order, 64x64 with an 8x8 coarsest grid, residual 1e-8

@@ -2,7 +2,7 @@
 to the relative residual 1e-8 of forward Euler (global step), single-level
 fast sweeping (four-direction steps, each followed by the mass correction)
 and the NMG solver, all from the global Maxwellian, for the cavity setups of
-Sec. 5 (single lid-driven, Tables 1 and 2; four-sided, Table 6; bottom-
+Sec. 4 (single lid-driven, Tables 1 and 2; four-sided, Table 6; bottom-
 heated, Table 8; second order, Table 9).  The iteration counts belong to the
 method and can be compared with the paper's; wall times are this GPU's.
 

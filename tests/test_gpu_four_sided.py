@@ -1,5 +1,5 @@
 """GPU: the four-sided lid-driven cavity with anti-parallel wall motion
-(Sec. 5.3): every wall moves, opposite walls the opposite way."""
+(Sec. 4.2): every wall moves, opposite walls the opposite way."""
 import numpy as np
 import pytest
 

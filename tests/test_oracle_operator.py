@@ -91,7 +91,7 @@ def _rot180(s, st):
 @pytest.mark.parametrize("case", CASES)
 def test_rotation_equivariance_four_sided(orc, case):
     # (x, y) -> (Lx - x, Ly - y) with every wall moving (the four-sided
-    # cavity of Sec. 5.3: u_N = -u_S, u_E = -u_W, opposite walls at equal
+    # cavity of Sec. 4.2: u_N = -u_S, u_E = -u_W, opposite walls at equal
     # temperature): the configuration is its own rotation, so
     # R(rot f) = rot R(f)
     s = small(case, wall_u=[-0.21, 0.3, 0.21, -0.3], wall_theta=[1.2, 0.9, 1.2, 0.9])
