@@ -6,7 +6,7 @@ Sec. 4 (single lid-driven, Tables 1 and 2; four-sided, Table 6; bottom-
 heated, Table 8; second order, Table 9).  The iteration counts belong to the
 method and can be compared with the paper's; wall times are this GPU's.
 
-    python -m paper_2206_13164_amd.paper_tables [--max-side 128] [--out FILE]
+    python -m paper_2206_13164_amd.paper_tables [--min-side 0] [--max-side 128] [--out FILE]
 
 Prints one JSON line per row.
 """
@@ -95,13 +95,14 @@ def euler_run(spec, max_steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--max-side", type=int, default=128)
+    ap.add_argument("--min-side", type=int, default=0)
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
     lines = []
     for table, label, kw, paper in ROWS:
-        if kw["nx"] > args.max_side:
+        if kw["nx"] > args.max_side or kw["nx"] < args.min_side:
             continue
         s = row_spec(kw)
         row = {"table": table, "case": label, "paper_iterations": dict(zip(("euler", "fs", "nmg"), paper))}
