@@ -12,12 +12,16 @@
  * the benchmark may load it.
  *
  * Parity pins (tests/test_oracle_*.py): basis change, xi-multiplication,
- * normalisation, macroscopic relations, Shakhov equilibrium and the
+ * normalisation, macroscopic relations, Shakhov and ES-BGK equilibria and the
  * regularisation term against Gauss-Hermite quadrature; the wall half-range
  * integrals against adaptive quadrature; C_{M+1} against the Hermite roots;
+ * the second-order operator (reconstruction, face and in-cell
+ * regularisation) converging at second order to the semi-discrete
+ * regularised system; the norm weights against the Maxwellian-weighted
+ * inner product; the coarse-grid correction against quadrature projections;
  * operator invariants (Maxwellian fixed point, mass conservation, mirror and
  * transpose equivariance); serial == wavefront sweep; FS == explicit Euler
- * steady state.  The exact flux/boundary/norm choices of the paper's own code
+ * steady state.  The exact flux/boundary choices of the paper's own code
  * are not printed in the paper: "parity unpinned" against the paper's
  * numbers, pinned only by the invariants above.
  */
@@ -226,12 +230,73 @@ void orc_macro(int M, const double *rec, double *out) {
 }
 
 /* BGK-type relaxation Q = nu (f^E - f), eq. (5), with the collision
- * frequency of eq. (29).  BGK: f^E is the local Maxwellian, eq. (6), whose
- * only coefficient in the cell's own basis is f^E_0 = rho.  Shakhov, eq. (8):
+ * frequency of eq. (29) (beta is the problem's: 1 for Shakhov, Pr for
+ * ES-BGK in Sec. 4).  BGK: f^E is the local Maxwellian, eq. (6), whose
+ * only coefficient in the cell's own basis is f^E_0 = rho.  ES-BGK, eq. (7):
+ * esbgk_equilibrium above.  Shakhov, eq. (8):
  * (1-Pr)(xi-u).q/(5 rho th^2)(|xi-u|^2/th - 5) expands in Hermite
  * polynomials to (1-Pr)/(5 rho th^(3/2)) sum_i q_i (He_{3e_i} +
  * sum_{d!=i} He_{e_i+2e_d}), giving f^E_{3e_i} = f^E_{e_i+2e_d} =
  * (1-Pr) q_i / 5.  Requires M >= 3. */
+/* ES-BGK equilibrium, eq. (7): the Gaussian of density rho, mean u and
+ * covariance Lambda = th I + (1 - 1/Pr) sigma / rho.  Its coefficients in the
+ * basis [u, th] of the same mean follow from the generating function of the
+ * Hermite polynomials: for z = (xi - u)/sqrt(th) distributed normally with
+ * covariance I + B, sum_alpha E[He_alpha(z)] t^alpha / alpha! =
+ * exp(t^T B t / 2), and f_alpha = (th^{|alpha|/2} / alpha!) rho E[He_alpha(z)].
+ * With B = (Lambda - th I) / th the powers of th cancel:
+ *   f^E_alpha = rho [t^alpha] exp(t^T A t / 2),  A = Lambda - th I,
+ * i.e. the truncated power series sum_k (t^T A t / 2)^k / k! of degree <= M,
+ * formed here by repeated polynomial multiplication. */
+static void esbgk_equilibrium(const orc_problem *P, const double *rec, double *fE) {
+  int M = P->M;
+  const idxset *s = idx_of(M);
+  int N = s->N;
+  double mac[11];
+  orc_macro(M, rec, mac);
+  double rho = mac[0];
+  /* sigma_ij from eq. (10); sigma_13 = sigma_23 = 0 in this 2-D setting but
+   * written out in full */
+  double sig[3][3];
+  sig[0][0] = mac[4]; sig[0][1] = sig[1][0] = mac[5]; sig[1][1] = mac[6]; sig[2][2] = mac[7];
+  sig[0][2] = sig[2][0] = rec[3 + P3(s, 1, 0, 1)];
+  sig[1][2] = sig[2][1] = rec[3 + P3(s, 0, 1, 1)];
+  double A[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) A[i][j] = (1.0 - 1.0 / P->Pr) * sig[i][j] / rho;
+  /* q(t) = t^T A t / 2 as a polynomial (coefficients indexed like f) */
+  double *q = (double *)calloc(N, sizeof(double));
+  double *term = (double *)calloc(N, sizeof(double));
+  double *next = (double *)calloc(N, sizeof(double));
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      int b[3] = {0, 0, 0};
+      b[i] += 1; b[j] += 1;
+      int ib = P3(s, b[0], b[1], b[2]);
+      if (ib >= 0) q[ib] += 0.5 * A[i][j];
+    }
+  /* exp(q) = sum_k q^k / k!, truncated at degree M */
+  for (int al = 0; al < N; ++al) fE[al] = 0.0;
+  term[0] = 1.0;
+  for (int k = 0; 2 * k <= M; ++k) {
+    for (int al = 0; al < N; ++al) fE[al] += term[al];
+    /* next = term * q / (k + 1) */
+    for (int al = 0; al < N; ++al) next[al] = 0.0;
+    for (int a = 0; a < N; ++a) {
+      if (term[a] == 0.0) continue;
+      for (int b = 0; b < N; ++b) {
+        if (q[b] == 0.0) continue;
+        int c = P3(s, s->a[3 * a] + s->a[3 * b], s->a[3 * a + 1] + s->a[3 * b + 1],
+                   s->a[3 * a + 2] + s->a[3 * b + 2]);
+        if (c >= 0) next[c] += term[a] * q[b] / (k + 1);
+      }
+    }
+    memcpy(term, next, sizeof(double) * N);
+  }
+  for (int al = 0; al < N; ++al) fE[al] *= rho;
+  free(q); free(term); free(next);
+}
+
 void orc_collision(const orc_problem *P, const double *rec, double *Q) {
   int M = P->M;
   const idxset *s = idx_of(M);
@@ -240,6 +305,7 @@ void orc_collision(const orc_problem *P, const double *rec, double *Q) {
   double nu = P->beta * sqrt(M_PI / 2.0) * rho * pow(th, 1.0 - P->omega) / P->Kn;
   double *fE = (double *)calloc(s->N, sizeof(double));
   fE[0] = rho;
+  if (P->collision == 2) esbgk_equilibrium(P, rec, fE);
   if (P->collision == 1) {
     double mac[11];
     orc_macro(M, rec, mac);

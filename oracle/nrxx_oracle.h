@@ -29,7 +29,7 @@ typedef struct {
   int nx, ny;           /* finest grid */
   double lx, ly;        /* domain size */
   int M;                /* expansion order, >= 3 */
-  int collision;        /* 0 = BGK, 1 = Shakhov */
+  int collision;        /* 0 = BGK, 1 = Shakhov, 2 = ES-BGK */
   double Pr, Kn, omega, beta; /* nu = beta sqrt(pi/2) rho theta^(1-omega) / Kn */
   int order;            /* 1 or 2 (spatial reconstruction) */
   int limiter;          /* 0 = minmod, 1 = central slopes */
