@@ -218,6 +218,29 @@ int nrxx_sweep_stats(nrxx_ctx *ctx, double *ms_out, double *cell_updates_out,
  * partially completed sweep.  The context stays usable. */
 int nrxx_set_wait_limit(nrxx_ctx *ctx, double seconds);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the defect
+ * and norm of nrxx_residual without a context.  `p` describes the problem
+ * (validated as by nrxx_create: NRXX_EINVAL), `level` selects its level
+ * (0 = finest); state, rhs (NULL: r = 0) and R_out (may be NULL) are device
+ * record arrays of that level, owned by the caller, in the layout above.
+ * Results equal nrxx_residual's on a context of `p`, bit for bit.
+ * norm_dev (device, one double, may be NULL) receives the eq. (28) norm
+ * without synchronising; norm_host (host, may be NULL) receives it after
+ * the call synchronises the stream.  Work is enqueued on hip_stream
+ * (a hipStream_t, NULL = the null stream).
+ * The call allocates nothing: the per-cell scratch of the norm lives in a
+ * fixed device array of the library, NRXX_NOALLOC_MAX_CELLS + 64 doubles
+ * (2 MiB) per GPU, held by each GPU it runs on until the process ends; a
+ * norm of a level with more cells is refused (NRXX_EINVAL).  Every call on
+ * one GPU shares that GPU's array: calls that overlap on one GPU (different
+ * streams or host threads) race and must be serialised by the caller.
+ * Errors: text via nrxx_last_error(NULL). */
+#define NRXX_NOALLOC_MAX_CELLS 262144
+int nrxx_residual_noalloc(const nrxx_problem *p, int32_t level, const double *state,
+                          const double *rhs, double *R_out, double *norm_dev, double *norm_host,
+                          void *hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Batches: many independent problems solved together on one device.
  *

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnrxx.so")
-SOURCES = ["nrxx_kernels.hip", "nrxx_batch.hip", "nrxx_api.cpp", "nrxx_batch_api.cpp", "nrxx_mlp.hip"]
+SOURCES = ["nrxx_kernels.hip", "nrxx_batch.hip", "nrxx_api.cpp", "nrxx_batch_api.cpp", "nrxx_mlp.hip",
+           "nrxx_noalloc.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

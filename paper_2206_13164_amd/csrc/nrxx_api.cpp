@@ -17,7 +17,9 @@ using namespace nrxx;
 
 namespace {
 
-thread_local std::string g_create_error;
+// text of the last failed call that has no context (nrxx_create, the
+// context-free entry points); a fixed buffer, so setting it allocates nothing
+thread_local char g_create_error[512];
 
 // Largest root of He_n: largest eigenvalue of the symmetric tridiagonal
 // (Jacobi) matrix of the probabilists' Hermite recurrence (off-diagonal
@@ -51,10 +53,10 @@ double largest_hermite_root(int n) {
 // and int_{-inf}^0 He_m e^{-w^2/2} = (-1)^m int_0^inf He_m e^{-w^2/2}, with
 // int_0^inf He_0 = sqrt(pi/2) and int_0^inf He_m = He_{m-1}(0) for m >= 1.
 void wall_entering_constants(int M, double *out) {
-  std::vector<double> h0(M + 3);  // He_m(0)
+  double h0[MMAX + 3];  // He_m(0), m <= M + 2 (fixed size: no allocation)
   h0[0] = 1.0;
   h0[1] = 0.0;
-  for (int m = 1; m + 1 < (int)h0.size(); ++m) h0[m + 1] = -m * h0[m - 1];
+  for (int m = 1; m + 1 < M + 3; ++m) h0[m + 1] = -m * h0[m - 1];
   auto neg_half = [&](int m) {  // (2 pi)^-1/2 int_{-inf}^0 He_m e^{-w^2/2}
     double pos = m == 0 ? 0.5 : h0[m - 1] / sqrt(2.0 * M_PI);
     return (m % 2 == 0) ? pos : -pos;
@@ -118,7 +120,7 @@ int fail(nrxx_ctx *c, int code, const char *fmt, ...) {
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
   if (c) c->err = buf;
-  else g_create_error = buf;
+  else snprintf(g_create_error, sizeof g_create_error, "%s", buf);
   return code;
 }
 
@@ -363,18 +365,36 @@ int mass_fix_impl(nrxx_ctx *c, double *st) {
 namespace nrxx {
 
 namespace {
-bool bad(std::string &msg, const char *fmt, ...) {
-  char buf[512];
+struct MsgBuf {
+  char *p;
+  size_t n;
+};
+bool bad(MsgBuf msg, const char *fmt, ...) {
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
+  if (msg.p && msg.n) vsnprintf(msg.p, msg.n, fmt, ap);
   va_end(ap);
-  msg = buf;
   return false;
 }
 }  // namespace
 
+int set_context_free_error(int code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_create_error, sizeof g_create_error, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
 bool validate_problem(const nrxx_problem &P, std::string &msg) {
+  char buf[512] = {0};
+  const bool ok = validate_problem(P, buf, sizeof buf);
+  if (!ok) msg = buf;
+  return ok;
+}
+
+bool validate_problem(const nrxx_problem &P, char *msg_buf, size_t cap) {
+  const MsgBuf msg{msg_buf, cap};
   if (P.M < MMIN || P.M > MMAX) return bad(msg, "M = %d outside [%d, %d]", P.M, MMIN, MMAX);
   if (P.levels < 1 || P.levels > 16) return bad(msg, "levels = %d", P.levels);
   if (P.nx < 1 || P.ny < 1) return bad(msg, "grid %d x %d", P.nx, P.ny);
@@ -597,7 +617,7 @@ int nrxx_destroy(nrxx_ctx *c) {
   return NRXX_OK;
 }
 
-const char *nrxx_last_error(const nrxx_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+const char *nrxx_last_error(const nrxx_ctx *c) { return c ? c->err.c_str() : g_create_error; }
 
 int nrxx_level_shape(const nrxx_ctx *c, int level, int32_t *nx, int32_t *ny) {
   if (!level_ok(c, level) || !nx || !ny) return NRXX_EINVAL;

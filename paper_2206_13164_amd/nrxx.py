@@ -54,6 +54,8 @@ EXPORTS = {
     "nrxx_level_schedule": (c_int, [c_void_p, c_int]),
     "nrxx_init_maxwellian": (c_int, [c_void_p, c_int, c_void_p, c_double, c_double, c_double, c_double]),
     "nrxx_residual": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double)]),
+    "nrxx_residual_noalloc": (c_int, [ctypes.POINTER(Problem), c_int, c_void_p, c_void_p, c_void_p,
+                                      c_void_p, ctypes.POINTER(c_double), c_void_p]),
     "nrxx_sweep": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_int, c_int]),
     "nrxx_restrict": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "nrxx_fas_rhs": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
@@ -142,6 +144,30 @@ def _ptr(t):
     if t is None:
         return None
     return c_void_p(t.data_ptr())
+
+
+NOALLOC_MAX_CELLS = 262144  # NRXX_NOALLOC_MAX_CELLS of include/nrxx.h
+
+
+def residual_noalloc(spec, state, level=0, rhs=None, out=None, norm_dev=None, host_norm=True,
+                     stream=None):
+    """nrxx_residual_noalloc: the defect (into `out`, may be None) and the
+    eq. (28) norm of `state` on `level` of the problem `spec`, without a
+    context and without allocating.  `norm_dev` (a 1-element float64 CUDA
+    tensor, may be None) receives the norm on the device; with host_norm the
+    call synchronises and returns it (else returns None)."""
+    import torch
+    L = load()
+    P = problem(spec)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    nrm = c_double()
+    rc = L.nrxx_residual_noalloc(ctypes.byref(P), level, _ptr(state), _ptr(rhs), _ptr(out),
+                                 _ptr(norm_dev), ctypes.byref(nrm) if host_norm else None,
+                                 c_void_p(stream.cuda_stream))
+    if rc != NRXX_OK:
+        raise NrxxError(rc, L.nrxx_last_error(None).decode())
+    return nrm.value if host_norm else None
 
 
 class Context:

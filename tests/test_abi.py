@@ -85,3 +85,23 @@ def test_batch_null_arguments():
     assert L.nrxx_batch_destroy(None) == N.NRXX_OK
     assert L.nrxx_batch_groups(None) == N.NRXX_EINVAL
     assert L.nrxx_batch_solve(None, None, 1e-8, 1, 0, None, None, None) == N.NRXX_EINVAL
+
+
+def test_noalloc_residual_checks_arguments_on_the_host():
+    """nrxx_residual_noalloc refuses bad problems, levels, NULL states and
+    levels larger than its fixed scratch array before any device work (the
+    state pointer below is never dereferenced)."""
+    L = N.load()
+    nrm = ctypes.c_double(7.0)
+    fake = ctypes.c_void_p(256)
+    assert L.nrxx_residual_noalloc(None, 0, fake, None, None, None, ctypes.byref(nrm), None) == N.NRXX_EINVAL
+    bad = N.problem(I.spec("lid32_bgk_m3", M=9))
+    assert L.nrxx_residual_noalloc(ctypes.byref(bad), 0, fake, None, None, None, ctypes.byref(nrm), None) == N.NRXX_EINVAL
+    ok = N.problem(I.spec("lid32_bgk_m3"))
+    assert L.nrxx_residual_noalloc(ctypes.byref(ok), 2, fake, None, None, None, ctypes.byref(nrm), None) == N.NRXX_EINVAL
+    assert L.nrxx_residual_noalloc(ctypes.byref(ok), 0, None, None, None, None, ctypes.byref(nrm), None) == N.NRXX_EINVAL
+    big = N.problem(I.spec("lid32_bgk_m3", nx=1024, ny=512))  # 524288 cells
+    assert L.nrxx_residual_noalloc(ctypes.byref(big), 0, fake, None, None, None, ctypes.byref(nrm), None) == N.NRXX_EINVAL
+    assert b"scratch" in L.nrxx_last_error(None)
+    assert N.NOALLOC_MAX_CELLS == 262144
+    assert nrm.value == 7.0

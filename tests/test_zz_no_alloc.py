@@ -1,0 +1,43 @@
+"""The context-free, allocation-free residual (nrxx_residual_noalloc) against
+the context residual (nrxx_residual) it is a variant of: same defect records
+and the same eq. (28) norm, bit for bit, on two calls in a row, the second on
+a smaller level (the shared scratch array keeps the first call's contents)."""
+import pytest
+
+from gpu_common import require_gpu
+from paper_2206_13164_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _spec(nx, ny, M, order):
+    return I.spec(None, nx=nx, ny=ny, M=M, collision=1, Pr=2.0 / 3.0, Kn=0.12, order=order,
+                  limiter=1, levels=2, wall_u=[0.0, 0.1, 0.3, 0.0],
+                  wall_theta=[1.4, 1.0, 1.0, 0.9])
+
+
+@pytest.mark.parametrize("M,order", [(5, 2), (3, 1)])
+def test_noalloc_residual_equals_context_residual(M, order):
+    torch = require_gpu()
+    from paper_2206_13164_amd import nrxx as N
+    # a larger problem first, then a smaller one: the second call must not
+    # see the first call's partial sums
+    for k, (nx, ny, level) in enumerate(((48, 40, 0), (20, 12, 1))):
+        s = _spec(nx, ny, M, order)
+        st = I.random_state(s, level=level, seed=31 + k, amp=0.07)
+        rhs = I.random_rhs(s, level, seed=41 + k)
+        ctx = N.Context(s)
+        d, r = ctx.to_device(st), ctx.to_device(rhs)
+        out_ctx, out_na = ctx.empty(level), ctx.empty(level)
+        n_ctx = ctx.residual(d, level=level, rhs=r, out=out_ctx)
+        ndev = torch.full((1,), -1.0, dtype=torch.float64, device="cuda")
+        print(f"noalloc M={M} order={order} grid={nx}x{ny} level={level}", flush=True)
+        n_na = N.residual_noalloc(s, d, level=level, rhs=r, out=out_na, norm_dev=ndev)
+        torch.cuda.synchronize()
+        assert torch.equal(out_ctx, out_na)
+        assert n_na == n_ctx
+        assert abs(ndev.item() - n_ctx) <= 1e-15 * n_ctx
+        # without rhs and without a defect output, norm only
+        n_ctx0 = ctx.residual(d, level=level)
+        assert N.residual_noalloc(s, d, level=level) == n_ctx0
+        ctx.close()
