@@ -1,11 +1,24 @@
-"""Benchmark: steady-state NRxx solve of the lid-driven cavity on one MI355X.
+"""Benchmark of the NRxx steady-state solver (FAS V-cycles over fast-sweeping
+smoothers, Alg. 1-2 of the paper) on one MI355X.  Prints one JSON line.
 
-A step is one full solve (Alg. 2 V-cycles + mass correction + stop test,
-Sec. 3.2.3) from the global Maxwellian to the workload's tolerance, on the
-128x128 lid-driven cavity (Shakhov Pr 2/3, Kn 0.075, M = 5, second-order
-minmod, lid 0.5, 4-level V-cycle, tol 1e-10).  `value` is the whole-job
-smoother throughput: cell-moment updates made by fast-sweeping steps inside
-the timed region divided by the timed wall time.  Prints one JSON line.
+Headline workload: 64 lid-driven cavities drawn from rng(220613164) (side
+uniform in {64, 96, 128, 192, 256}, Kn log-uniform in [0.01, 1], lid speed
+uniform in [0.1, 0.5], M uniform in {3, 5, 8}, BGK or Shakhov at 50/50,
+second order with central slopes, walls at theta 1, levels down to an 8- or
+12-cell coarsest grid), solved together as one batch: autotuned sweep
+schedule, one graph-captured NMG iteration per group of equal (M, order).
+A step is one NMG iteration (V-cycle, mass correction, residual norm, stop
+test) of all 64 cavities.  `value` = smoother cell-moment updates made in
+the timed steps / timed wall time.  `time_to_residual_s` = one solve of the
+whole batch from the global Maxwellian until every cavity has reached the
+relative residual 1e-8.
+
+Legs beside the headline: the bottom-heated 256x256 M = 8 cavity at
+Kn 0.05 and 0.2 in FP64 and with FP32 smoothing blocks (mirror symmetry,
+field difference), held-out 256x256 M = 5 cavities from the Maxwellian and
+from the learned warm start, the single 128x128 M = 5 cavity, and the FP64
+oracle on the host cores (one thread in the serial order and all threads in
+the anti-diagonal order, plus a whole 32x32 M = 3 solve).
 """
 from __future__ import annotations
 
@@ -13,6 +26,7 @@ import argparse
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -21,10 +35,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "smoother cell-moment updates/s + time-to-residual 1e-8, plain vs mixed/learned"
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2206_13164_amd", "csrc", f)
-               for f in ("nrxx_device.hpp", "nrxx_kernels.hip", "nrxx_batch.hip")]
+               for f in ("nrxx_device.hpp", "nrxx_kernels.hip", "nrxx_batch.hip", "nrxx_wave.hpp",
+                         "nrxx_wsweep.hip")]
 PROFILES = os.path.join(ROOT, "profiles")
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+HEADLINE = "batch64_lid_mixed"  # the 64 drawn cavities
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def per_update_cost(M: int, order: int, coarse: bool, fp_bytes: int = 8):
@@ -42,18 +62,19 @@ def per_update_cost(M: int, order: int, coarse: bool, fp_bytes: int = 8):
 
 
 def cycle_accounting(spec):
-    """Cell updates, launches, flops and bytes of the smoother in one V-cycle."""
+    """Cell updates, flops, bytes and dependent anti-diagonal steps of the
+    smoother in one V-cycle (gamma = 1)."""
     L = spec["levels"]
-    tot = dict(cells=0, launches=0, flops=0.0, bytes=0.0)
+    tot = dict(cells=0, flops=0.0, bytes=0.0, chain=0)
     for k in range(L):
         nx, ny = spec["nx"] >> k, spec["ny"] >> k
         steps = spec["s3"] if k == L - 1 else spec["s1"] + spec["s2"]
         fl, by = per_update_cost(spec["M"], spec["order"], coarse=k > 0)
         cells = steps * 4 * nx * ny
         tot["cells"] += cells
-        tot["launches"] += steps * 4 * (nx + ny - 1)
         tot["flops"] += cells * fl
         tot["bytes"] += cells * by
+        tot["chain"] += steps * 4 * (nx + ny - 1)
     return tot
 
 
@@ -76,7 +97,6 @@ def profiled_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` on `workload` from the committed
     FETCH_SIZE / WRITE_SIZE summary, or None when the summary is missing or
     was taken on a different kernel source."""
-    import hashlib
     path = os.path.join(PROFILES, f"{kernel}_{workload}.md")
     if not os.path.exists(path):
         return None
@@ -85,263 +105,340 @@ def profiled_traffic(kernel: str, workload: str):
         if ":" in line and line.startswith("- "):
             k, v = line[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    src = kernel_source_hash()
-    if vals.get("kernel_source_sha256") != src or "traffic_bytes_per_launch" not in vals:
+    if vals.get("kernel_source_sha256") != kernel_source_hash() or "traffic_bytes_per_launch" not in vals:
         return None
     return float(vals["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(spec, seconds_hint: float):
-    """The oracle (FP64, serial paper-order sweeps, one thread) on a bounded
-    sample: one V-cycle of the same workload from the Maxwellian start."""
-    import oracle
-    from paper_2206_13164_amd import inputs as I
-    oracle.set_threads(1)
-    P = oracle.problem(spec)
-    st = I.maxwellian_state(spec)
-    acc = cycle_accounting(spec)
+def host_cpu():
+    model = platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
+# ---------------------------------------------------------------------------
+# Headline: the 64-cavity batch
+# ---------------------------------------------------------------------------
+
+def time_to_residual(b, st, max_cycles):
+    """The whole batch from the Maxwellian until every cavity has reached
+    the relative residual 1e-8 (graph-replayed cycles); closes the batch."""
+    import torch
+    b.set_timing(False)
+    b.init_maxwellian(st)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    oracle.vcycle(P, st)
-    dt = time.perf_counter() - t0
-    N = math.comb(spec["M"] + 3, 3)
-    return {"value": acc["cells"] * N / dt, "unit": "cell-moment updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"one V-cycle ({acc['cells']} cell updates) of the same workload from the "
-                      f"Maxwellian start, serial Gauss-Seidel order, 1 thread, {dt:.1f} s"}
+    rc, cyc, nrm, ref = b.solve(st, 1e-8, max_cycles, use_graph=True)
+    torch.cuda.synchronize()
+    ttr = time.perf_counter() - t0
+    log(f"time to residual {ttr:.1f} s")
+    b.close()
+    return ttr, cyc, nrm, ref, rc
 
 
-def time_variant(spec, tol, max_cycles, ref, NA):
-    """One warm-up and one timed solve of a variant of the workload (same
-    start, same stopping rule): time-to-residual and cycle count."""
+def headline(args):
+    import torch
+    from paper_2206_13164_amd import inputs as I
+    from paper_2206_13164_amd import nrxx as N
+    specs = I.cavity_draws(64, I.SEED_BATCH)
+    NA = [math.comb(s["M"] + 3, 3) for s in specs]
+    acc = [cycle_accounting(s) for s in specs]
+    b = N.Batch(specs)
+    st = b.empty_states()
+    b.init_maxwellian(st)
+    t0 = time.perf_counter()
+    b.autotune(st)
+    tune_s = time.perf_counter() - t0
+    log(f"autotune {tune_s:.1f} s")
+    b.set_timing(True)
+    b.init_maxwellian(st)
+    b.solve(st, 0.0, max(1, args.warmup), use_graph=False)  # warm-up cycles
+    for g in range(b.groups()):
+        b.kernel_stats(g, reset=True)
+    torch.cuda.synchronize()
+    w0 = (time.monotonic_ns(), time.clock_gettime_ns(time.CLOCK_BOOTTIME))
+    t0 = time.perf_counter()
+    # eagerly enqueued cycles: HIP events around every sweep launch (events
+    # recorded by graph nodes report no elapsed time); the time-to-residual
+    # solve below replays the captured graphs
+    rc, cyc, nrm, ref = b.solve(st, 0.0, args.steps, use_graph=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    w1 = (time.monotonic_ns(), time.clock_gettime_ns(time.CLOCK_BOOTTIME))
+    # the timed window on the host clocks, to select its dispatches in a trace
+    log(f"timed window monotonic_ns {w0[0]} {w1[0]} boottime_ns {w0[1]} {w1[1]}")
+    assert all(int(c) == args.steps for c in cyc), cyc
+    upd = sum(args.steps * a["cells"] * n for a, n in zip(acc, NA))
+    # sweep kernels over the timed steps (HIP events on each group's stream)
+    groups, tot_ms, tot_launch, tot_flops, tot_bytes = [], 0.0, 0.0, 0.0, 0.0
+    for g in range(b.groups()):
+        t = b.tuning(g)
+        ms, nl, cf, cc = b.kernel_stats(g)
+        ff, bf = per_update_cost(t["M"], t["order"], coarse=False)
+        fc, bc = per_update_cost(t["M"], t["order"], coarse=True)
+        fl, by = cf * ff + cc * fc, cf * bf + cc * bc
+        tot_ms += ms
+        tot_launch += nl
+        tot_flops += fl
+        tot_bytes += by
+        groups.append({"M": t["M"], "order": t["order"], "problems": t["problems"],
+                       "kernel": "k_wsweep" if t["kernel"] == 1 else "k_bsweep",
+                       "team_width": t["team_width"], "grid": t["grid"], "unit_order": t["unit_order"],
+                       "split": t["split"], "launches": nl, "avg_launch_us": ms * 1e3 / max(nl, 1),
+                       "cell_updates": cf + cc, "achieved_tflops": fl / max(ms, 1e-30) / 1e9,
+                       "hbm_GBs": by / max(ms, 1e-30) / 1e6})
+    log(f"timed {args.steps} cycles in {wall:.2f} s")
+    if args.no_ttr:
+        b.close()
+        ttr, cyc2, nrm2, ref2, rc2 = float("nan"), [0], [0.0], [1.0], -1
+    else:
+        ttr, cyc2, nrm2, ref2, rc2 = time_to_residual(b, st, args.max_cycles)
+    achieved = tot_flops / max(tot_ms, 1e-30) / 1e9  # TFLOP/s per launch-second
+
+    gbs = tot_bytes / max(tot_ms, 1e-30) / 1e6
+    conv = [bool(nrm2[i] <= 1e-8 * ref2[i]) for i in range(len(nrm2))]
+    upd2 = sum(int(c) * a["cells"] * n for c, a, n in zip(cyc2, acc, NA))
+    out = {
+        "value": upd / wall,
+        "ms_per_step": wall / args.steps * 1e3,
+        "config": {
+            "workload": HEADLINE,
+            "problems": len(specs), "seed": I.SEED_BATCH,
+            "sides": sorted({s["nx"] for s in specs}), "M": sorted({s["M"] for s in specs}),
+            "Kn_range": [min(s["Kn"] for s in specs), max(s["Kn"] for s in specs)],
+            "order": 2, "limiter": "central", "collision": "BGK/Shakhov (Pr 2/3)",
+            "cell_values": sum(s["nx"] * s["ny"] * (n + 3) for s, n in zip(specs, NA)),
+            "step": "one NMG iteration (V-cycle + mass correction + norm + stop test) of all 64 "
+                    "cavities, enqueued eagerly with a HIP event pair around every sweep launch",
+            "start": "global Maxwellian",
+        },
+        "time_to_residual_s": ttr,
+        "time_to_residual": {"tol": 1e-8, "all_converged": all(conv) and rc2 == N.NRXX_OK,
+                             "measured": not args.no_ttr,
+                             "cycles_min": int(min(cyc2)), "cycles_mean": float(sum(cyc2)) / len(cyc2),
+                             "cycles_max": int(max(cyc2)), "cell_moment_updates_per_s": upd2 / ttr,
+                             "autotune_s": tune_s},
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS,
+            "traffic": None,
+            "kernel": "batched work-queue sweep kernels (k_wsweep: one wavefront per cell, or "
+                      "k_bsweep: cell teams, per group as autotuned; up to 8 directional sweeps "
+                      "of one level per launch)",
+            "launches": tot_launch,
+            "avg_launch_us": tot_ms * 1e3 / max(tot_launch, 1),
+            "flops_per_launch": tot_flops / max(tot_launch, 1),
+            "bytes_per_launch": tot_bytes / max(tot_launch, 1),
+            "hbm_achieved_GBs": gbs,
+            "hbm_frac": gbs / PEAK_HBM_GBS,
+            "note": "groups of different M run concurrently on their own streams, so their launch "
+                    "durations overlap; flops per launch are the algorithmic estimate per cell "
+                    "update times the updates of that launch",
+            "groups": groups,
+        },
+    }
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Legs
+# ---------------------------------------------------------------------------
+
+def mirror_x(rec, M):
+    """The x-mirror image of a state: cells i -> nx-1-i, u1 -> -u1 and
+    coefficients with odd alpha_1 change sign."""
+    from paper_2206_13164_amd import inputs as I
+    import numpy as np
+    al = I.alpha_list(M)
+    m = rec[:, ::-1, :].copy()
+    m[..., 0] = -m[..., 0]
+    odd = al[:, 0] % 2 == 1
+    m[..., 3:][..., odd] *= -1.0
+    return m
+
+
+def state_err(a, b, M):
+    import numpy as np
+    from paper_2206_13164_amd import inputs as I
+    n = I.alpha_list(M).sum(axis=1)
+    rho, th = b[..., 3], b[..., 2]
+    eu = (np.abs(a[..., :2] - b[..., :2]).max(axis=-1) / np.sqrt(th)).max()
+    et = (np.abs(a[..., 2] - b[..., 2]) / th).max()
+    ef = (np.abs(a[..., 3:] - b[..., 3:]) / (rho[..., None] * th[..., None] ** (n / 2.0))).max()
+    return float(max(eu, et, ef))
+
+
+def solve_timed(spec, tol, max_cycles, ref=None):
+    """One warm-up cycle, then a timed solve from the Maxwellian; returns the
+    record, the final host state and the context's sweep statistics."""
     import torch
     from paper_2206_13164_amd import nrxx as N
     ctx = N.Context(spec)
     st = ctx.empty(0)
     ctx.init_maxwellian(st)
-    ctx.solve(st, tol, max_cycles, ref_norm=ref)
+    if ref is None:
+        ref = ctx.residual(st)
+    ctx.solve(st, 0.0, 1)
     ctx.init_maxwellian(st)
+    ctx.sweep_stats(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rc, cyc, hist = ctx.solve(st, tol, max_cycles, ref_norm=ref)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    if rc != N.NRXX_OK:
-        raise SystemExit(f"variant did not converge: rc={rc} cycles={cyc} last={hist[-1]:.3e}")
-    ms, cells, _ = ctx.sweep_stats(reset=True)
+    sms, scells, slaunch = ctx.sweep_stats(reset=True)
+    host = ctx.to_host(st, math.comb(spec["M"] + 3, 3) + 3)
     ctx.close()
-    return {"precision": "fp32 sweeps + fp64 defect correction" if spec.get("precision") else "fp64",
-            "time_to_residual_s": wall, "cycles": cyc, "final_rel_residual": hist[-1] / ref}
+    acc = cycle_accounting(spec)
+    rec = {"precision": "fp32 smoothing blocks + fp64 defect correction" if spec.get("precision")
+           else "fp64", "seconds": wall, "cycles": cyc, "converged": rc == N.NRXX_OK,
+           "final_rel_residual": hist[-1] / ref,
+           "critical_path": {"dependent_steps_per_cycle": acc["chain"],
+                             "ms_per_cycle": wall / max(cyc, 1) * 1e3,
+                             "us_per_dependent_step": wall / max(cyc, 1) / acc["chain"] * 1e6},
+           "sweep_kernel": {"launches": slaunch, "avg_launch_us": sms * 1e3 / max(slaunch, 1),
+                            "share_of_wall": sms * 1e-3 / wall}}
+    return rec, host, ref
 
 
-def learned_leg(max_cycles):
-    """Config-5 comparison on a held-out cavity (256x256, M = 5, 6 levels,
-    tol 1e-8 relative to the Maxwellian start's residual): plain FP64 from
-    the Maxwellian vs the learned start in FP64 and with FP32 smoothing
-    blocks; times include the network's inference and the start check."""
+def heated_leg(max_cycles):
+    """The bottom-heated 256x256 cavity (Shakhov, M = 8, central slopes,
+    5 levels) at Kn 0.05 and 0.2: FP64 and FP32-block solves to 1e-8, the
+    x-mirror asymmetry of the converged FP64 field and the difference between
+    the two converged fields."""
+    from paper_2206_13164_amd import inputs as I
+    out = {}
+    for name in ("heated256_shakhov_m8_kn005", "heated256_shakhov_m8_kn02"):
+        s = I.spec(name)
+        p0, h0, ref = solve_timed(s, s["tol"], max_cycles)
+        p1, h1, _ = solve_timed(dict(s, precision=1), s["tol"], max_cycles, ref=ref)
+        out[name] = {"Kn": s["Kn"], "fp64": p0, "fp32_blocks": p1,
+                     "speedup_fp32_blocks": p0["seconds"] / p1["seconds"],
+                     "mirror_asymmetry_fp64": state_err(mirror_x(h0, 8), h0, 8),
+                     "mirror_asymmetry_fp32_blocks": state_err(mirror_x(h1, 8), h1, 8),
+                     "fp32_blocks_vs_fp64_field": state_err(h1, h0, 8)}
+        log(f"{name}: fp64 {p0['seconds']:.2f} s, fp32 blocks {p1['seconds']:.2f} s")
+    return out
+
+
+def learned_leg(draws, max_cycles):
+    """Held-out 256x256 M = 5 cavities (rng(220613166)): plain FP64 from the
+    Maxwellian against the learned start in FP64 and with FP32 smoothing
+    blocks, each to 1e-8 relative to the Maxwellian start's residual; the
+    learned times include the network's inference and the start check."""
     from paper_2206_13164_amd import inputs as I
     from paper_2206_13164_amd import warmstart as W
     if not os.path.exists(W.DEFAULT_WEIGHTS):
         return {"skipped": "no trained network"}
     ws = W.WarmStart()
-    s = I.cavity_draws(1, I.SEED_TEST, sides=(256,), Ms=(5,), levels=6)[0]
-    r = W.compare(s, ws, tol=1e-8, max_cycles=max_cycles)
-    base = r["maxwellian_p0"]["seconds"]
-    return {"cavity": {"grid": "256x256", "M": 5, "Kn": s["Kn"], "lid": s["wall_u"][2],
-                       "collision": "Shakhov" if s["collision"] else "BGK", "levels": 6,
-                       "tol": 1e-8},
-            **r,
-            "speedup_learned_fp64": base / r["learned_p0"]["seconds"],
-            "speedup_learned_mixed": base / r["learned_p1"]["seconds"],
+    rows = []
+    for s in I.cavity_draws(draws, I.SEED_TEST, sides=(256,), Ms=(5,), levels=6):
+        r = W.compare(s, ws, tol=1e-8, max_cycles=max_cycles)
+        base = r["maxwellian_p0"]["seconds"]
+        rows.append({"Kn": s["Kn"], "lid": s["wall_u"][2],
+                     "collision": "Shakhov" if s["collision"] else "BGK", **r,
+                     "speedup_learned_fp64": base / r["learned_p0"]["seconds"],
+                     "speedup_learned_fp32_blocks": base / r["learned_p1"]["seconds"]})
+        log(f"learned draw Kn {s['Kn']:.3f}: {base:.2f} s -> {r['learned_p1']['seconds']:.2f} s")
+    tot0 = sum(r["maxwellian_p0"]["seconds"] for r in rows)
+    tot1 = sum(r["learned_p1"]["seconds"] for r in rows)
+    return {"grid": "256x256", "M": 5, "levels": 6, "tol": 1e-8, "draws": rows,
+            "total_seconds_maxwellian_fp64": tot0, "total_seconds_learned_fp32_blocks": tot1,
+            "speedup_total": tot0 / tot1,
             "network": {k: v for k, v in ws.meta.items() if k != "loss"}}
 
 
-def baselines_leg(spec, max_cycles):
-    """The paper's comparison of solvers (Sec. 2.4, 3.1, 3.2) on the first-order
-    version of the workload: the NMG solve to the workload's tolerance, then
-    explicit time marching (forward Euler, global step) and single-level fast
-    sweeping from the same Maxwellian start for the same wall time, each with
-    the relative residual it reaches and its cell-update rate.  Forward Euler
-    with the unlimited central slopes of the second-order workload itself
-    turns non-physical; the steps it survives there are reported too."""
-    import torch
-    from paper_2206_13164_amd import nrxx as N
-    NA = math.comb(spec["M"] + 3, 3)
-    cells = spec["nx"] * spec["ny"]
-    s1 = dict(spec, order=1)
-    ctx = N.Context(s1)
-    st = ctx.empty(0)
-    ctx.init_maxwellian(st)
-    ref = ctx.residual(st)
-    ctx.solve(st, spec["tol"], max_cycles, ref_norm=ref)
-    ctx.init_maxwellian(st)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rc, cyc, hist = ctx.solve(st, spec["tol"], max_cycles, ref_norm=ref)
-    torch.cuda.synchronize()
-    budget = time.perf_counter() - t0
-    out = {"workload": "first-order version of the benchmark cavity", "budget_s": budget,
-           "nmg": {"cycles": cyc, "seconds": budget, "rel_residual": hist[-1] / ref,
-                   "converged": rc == N.NRXX_OK}}
-
-    def march(c, st, step, chunk):
-        c.init_maxwellian(st)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        n = 0
-        while time.perf_counter() - t0 < budget:
-            step(st, chunk)
-            n += chunk
-        torch.cuda.synchronize()
-        return n, time.perf_counter() - t0
-
-    ctx.euler(st, nsteps=10)  # load the code objects
-    n, wall = march(ctx, st, lambda x, k: ctx.euler(x, nsteps=k), 200)
-    out["euler"] = {"steps": n, "seconds": wall, "rel_residual": ctx.residual(st) / ref,
-                    "cell_moment_updates_per_s": n * cells * NA / wall}
-    ctx.close()
-    ctx = N.Context(dict(s1, levels=1))
-    st = ctx.empty(0)
-    ctx.init_maxwellian(st)
-    ctx.sweep(st, nsteps=1)
-    def fs_steps(x, k):
-        ctx.sweep(x, nsteps=k)
-        torch.cuda.synchronize()  # sweeps are asynchronous: keep the clock honest
-
-    n, wall = march(ctx, st, fs_steps, 4)
-    out["fast_sweeping_single_level"] = {
-        "steps": n, "seconds": wall, "rel_residual": ctx.residual(st) / ref,
-        "cell_moment_updates_per_s": 4 * n * cells * NA / wall}
-    ctx.close()
-    ctx = N.Context(spec)
-    st = ctx.empty(0)
-    ctx.init_maxwellian(st)
-    n = 0
-    try:
-        while n < 20000:
-            ctx.euler(st, nsteps=100)
-            n += 100
-        out["euler_second_order_central"] = {"steps": n, "non_physical": False}
-    except N.NrxxError:
-        out["euler_second_order_central"] = {"steps_before_non_physical": n, "non_physical": True}
-    ctx.close()
-    return out
-
-
-def four_sided_leg(max_cycles):
-    """The paper's solver table for the four-sided cavity (Sec. 4.2, 64x64,
-    M = 5, Shakhov, Kn 0.777): iterations and wall time to the relative
-    residual 1e-8 of forward Euler (steps of the global step), single-level
-    fast sweeping (four-direction steps, each followed by the mass
-    correction) and NMG (V-cycles), all from the global Maxwellian.  The
-    paper's CPU figures are quoted beside them as context."""
-    import torch
+def single_leg(workload, max_cycles):
+    """One cavity alone (latency-bound: one cell team per cell on the
+    dependency chain of the sweeps)."""
     from paper_2206_13164_amd import inputs as I
-    from paper_2206_13164_amd import nrxx as N
-    s = I.spec("four_sided64_shakhov_m5")
-    tol = s["tol"]
-    out = {"workload": "four_sided64_shakhov_m5", "tol": tol,
-           "paper_cpu": {"iterations": {"euler": 4442, "fast_sweeping": 607, "nmg": 17},
-                         "seconds": {"euler": 6031.19, "fast_sweeping": 2068.4, "nmg": 295.75}}}
-
-    def timed_solve(spec):
-        ctx = N.Context(spec)
-        st = ctx.empty(0)
-        ctx.init_maxwellian(st)
-        ref = ctx.residual(st)
-        ctx.solve(st, tol, 2, ref_norm=ref)  # load the code objects
-        ctx.init_maxwellian(st)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rc, cyc, hist = ctx.solve(st, tol, max_cycles, ref_norm=ref)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ctx.close()
-        return {"iterations": cyc, "seconds": wall, "converged": rc == N.NRXX_OK,
-                "rel_residual": hist[-1] / ref}
-
-    out["nmg"] = timed_solve(s)
-    out["fast_sweeping"] = timed_solve(dict(s, levels=1, s3=1))
-    ctx = N.Context(s)
-    st = ctx.empty(0)
-    ctx.init_maxwellian(st)
-    ref = ctx.residual(st)
-    ctx.euler(st, nsteps=2)
-    ctx.init_maxwellian(st)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    n, r = 0, ref
-    while r > tol * ref and n < 20000:
-        ctx.euler(st, nsteps=1)
-        n += 1
-        r = ctx.residual(st)
-    wall = time.perf_counter() - t0
-    ctx.close()
-    out["euler"] = {"iterations": n, "seconds": wall, "converged": r <= tol * ref,
-                    "rel_residual": r / ref}
-    return out
+    s = I.spec(workload)
+    rec, _, _ = solve_timed(s, s["tol"], max_cycles)
+    NA = math.comb(s["M"] + 3, 3)
+    rec["workload"] = workload
+    rec["cell_moment_updates_per_s"] = rec["cycles"] * cycle_accounting(s)["cells"] * NA / rec["seconds"]
+    return rec
 
 
-def batch_leg(n=16, cycles=6):
-    """Batched throughput: n drawn cavities (sides 64/96/128, M 3/5/8,
-    BGK/Shakhov, Kn log-uniform in [0.01, 1]) in one batch after autotuning,
-    `cycles` graph-replayed V-cycles."""
-    import torch
+def cpu_baseline():
+    """The FP64 oracle on the host: one V-cycle of the first drawn cavity of
+    the batch (64x64, M = 8, BGK, 4 levels) from the Maxwellian, once in the
+    serial order on one thread and once in the anti-diagonal order on every
+    usable core (bitwise the same result), plus a whole solve of the
+    32x32 M = 3 BGK cavity to 1e-8 on every core."""
+    import numpy as np
+    import oracle
     from paper_2206_13164_amd import inputs as I
-    from paper_2206_13164_amd import nrxx as N
-    specs = I.cavity_draws(n, I.SEED_BATCH, sides=(64, 96, 128))
-    b = N.Batch(specs)
-    st = b.empty_states()
-    b.init_maxwellian(st)
-    b.autotune(st)
-    b.solve(st, 0.0, 1)  # capture the graphs, load the code objects
-    b.init_maxwellian(st)
-    torch.cuda.synchronize()
+    model, ncpu, usable = host_cpu()
+    s = I.cavity_draws(1, I.SEED_BATCH)[0]
+    NA = math.comb(s["M"] + 3, 3)
+    cells = cycle_accounting(s)["cells"]
+    P = oracle.problem(s)
+    res = {}
+    for mode, threads in (("serial_1_thread", 1), ("antidiagonal_all_cores", usable)):
+        oracle.set_threads(threads)
+        oracle.set_vcycle_wavefront(threads > 1)
+        st = I.maxwellian_state(s)
+        t0 = time.perf_counter()
+        oracle.vcycle(P, st)
+        dt = time.perf_counter() - t0
+        res[mode] = {"threads": threads, "seconds": dt, "cell_moment_updates_per_s": cells * NA / dt}
+        res.setdefault("_states", []).append(st)
+    same = bool(np.array_equal(*res.pop("_states")))
+    c1 = I.spec("lid32_bgk_m3")
+    P1 = oracle.problem(c1)
+    st = I.maxwellian_state(c1)
     t0 = time.perf_counter()
-    rc, cyc, nrm, ref = b.solve(st, 0.0, cycles, use_graph=True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    upd = sum(int(c) * cycle_accounting(x)["cells"] * math.comb(x["M"] + 3, 3) for c, x in zip(cyc, specs))
-    tun = [b.tuning(g) for g in range(b.groups())]
-    b.close()
-    return {"problems": n, "cycles": cycles, "seconds": wall,
-            "cell_moment_updates_per_s": upd / wall,
-            "tuning": [{k: t[k] for k in ("M", "order", "problems", "team_width", "grid", "unit_order")}
-                       for t in tun]}
+    rc, cyc, hist = oracle.solve(P1, st, c1["tol"], 200)
+    c1_s = time.perf_counter() - t0
+    oracle.set_vcycle_wavefront(False)
+    oracle.set_threads(1)
+    best = res["antidiagonal_all_cores"]
+    return {"value": best["cell_moment_updates_per_s"], "unit": "cell-moment updates/s",
+            "cores": usable, "kind": "oracle",
+            "sample": f"one V-cycle ({cells} cell updates, N_alpha {NA}) of the batch's first cavity "
+                      f"(64x64, M = 8, BGK, Kn {s['Kn']:.3f}, 4 levels) from the Maxwellian, "
+                      f"anti-diagonal order on {usable} threads ({best['seconds']:.1f} s)",
+            "cpu_model": model, "nproc": ncpu, "usable_cores": usable, **res,
+            "parallel_equals_serial": same,
+            "lid32_bgk_m3_time_to_residual": {"seconds": c1_s, "cycles": cyc, "threads": usable,
+                                              "converged": rc == 0}}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5, help="timed NMG iterations of the batch")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="lid128_shakhov_m5_central")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-learned", action="store_true",
-                    help="skip the learned warm-start comparison (256x256 held-out cavity)")
-    ap.add_argument("--no-batch", action="store_true", help="skip the batched-throughput leg")
-    ap.add_argument("--no-baselines", action="store_true",
-                    help="skip the explicit-Euler and single-level fast-sweeping comparison")
-    ap.add_argument("--no-mixed", action="store_true",
-                    help="skip the FP32-sweep (precision 1) solve of the same workload")
-    ap.add_argument("--max-cycles", type=int, default=200)
+    ap.add_argument("--max-cycles", type=int, default=400)
+    ap.add_argument("--legs", default="heated,learned,single,cpu",
+                    help="comma list of heated, learned, single, cpu (or 'none')")
+    ap.add_argument("--learned-draws", type=int, default=4)
+    ap.add_argument("--no-ttr", action="store_true",
+                    help="skip the batch's time-to-residual solve (profiling runs)")
+    ap.add_argument("--single-workload", default="lid128_shakhov_m5_central")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
-    ap.add_argument("--schedule", type=int, default=0,
-                    help="sweep schedule: 0 automatic (= 3), 1 per-diagonal launches, "
-                         "2 static persistent, 3 work queue with overlapping sweeps")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver's "
-              "multi-GPU decomposition is a design, not implemented.",
-              file=sys.stderr)
+              "multi-GPU decomposition is a design, not implemented.", file=sys.stderr)
         sys.exit(2)
-
     import torch
-    from paper_2206_13164_amd import inputs as I
-    from paper_2206_13164_amd import nrxx as N
-
     if args.copy_bytes:
-        # plain copy of a known size: reads and writes copy_bytes each
         src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
@@ -349,105 +446,21 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": args.copy_bytes}))
         return
-
-    spec = I.spec(args.workload, schedule=args.schedule)
-    tol = spec["tol"]
-    M = spec["M"]
-    NA = math.comb(M + 3, 3)
     torch.cuda.set_device(0)
-    ctx = N.Context(spec)
-    st = ctx.empty(0)
-    ctx.init_maxwellian(st)
-    ref = ctx.residual(st)
-
-    def one_solve():
-        ctx.init_maxwellian(st)
-        rc, cyc, hist = ctx.solve(st, tol, args.max_cycles, ref_norm=ref)
-        return rc, cyc, hist
-
-    for _ in range(args.warmup):
-        one_solve()
-    ctx.sweep_stats(reset=True)
-    sched = ctx.level_schedule(0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    cycles = []
-    for _ in range(args.steps):
-        rc, cyc, hist = one_solve()
-        cycles.append(cyc)
-        if rc != N.NRXX_OK:
-            raise SystemExit(f"solve did not converge: rc={rc} cycles={cyc} last={hist[-1]:.3e}")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    sweep_ms, sweep_cells, launches = ctx.sweep_stats(reset=True)
-    wall = t1 - t0
-    acc = cycle_accounting(spec)
-    ncyc = sum(cycles)
-    assert abs(sweep_cells - ncyc * acc["cells"]) < 0.5, (sweep_cells, ncyc * acc["cells"])
-    value = sweep_cells * NA / wall
-    avg_launch_s = sweep_ms * 1e-3 / launches
-    flops_per_launch = ncyc * acc["flops"] / launches
-    bytes_per_launch = ncyc * acc["bytes"] / launches
-    achieved_tflops = flops_per_launch / avg_launch_s / 1e12
-    achieved_gbs = bytes_per_launch / avg_launch_s / 1e9
-    kname = {3: "k_bsweep", 2: "k_sweep_persist"}.get(sched, "k_sweep_diag")
-    traffic = profiled_traffic(kname, args.workload)
-
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "cell-moment updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {
-            "workload": args.workload,
-            "grid": f"{spec['nx']}x{spec['ny']}", "M": M, "N_alpha": NA,
-            "collision": "Shakhov" if spec["collision"] else "BGK", "Kn": spec["Kn"],
-            "order": spec["order"], "limiter": "minmod" if spec["limiter"] == 0 else "central",
-            "levels": spec["levels"], "tol": tol, "start": "global Maxwellian",
-        },
-        "time_to_residual_s": wall / args.steps,
-        "cycles_per_solve": cycles,
-        "sweep_kernel_rate": sweep_cells * NA / (sweep_ms * 1e-3),
-        "sweep_share_of_wall": sweep_ms * 1e-3 / wall,
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved_tflops,
-            "peak": PEAK_FP64_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved_tflops / PEAK_FP64_TFLOPS,
-            "traffic": traffic,
-            "kernel": kname + {3: " (work queue: up to 8 overlapping directional sweeps of one level per "
-                                  "launch)",
-                               2: " (static persistent: up to 16 directional sweeps of one level per launch)"}
-                              .get(sched, " (one anti-diagonal of one sweep direction per launch)"),
-            "launches": launches,
-            "avg_launch_us": avg_launch_s * 1e6,
-            "flops_per_launch": flops_per_launch,
-            "bytes_per_launch": bytes_per_launch,
-            "hbm_achieved_GBs": achieved_gbs,
-            "hbm_frac": achieved_gbs / PEAK_HBM_GBS,
-        },
-    }
-    if not args.no_mixed:
-        out["mixed"] = time_variant(dict(spec, precision=1), tol, args.max_cycles, ref, NA)
-        out["mixed"]["speedup_vs_plain"] = (wall / args.steps) / out["mixed"]["time_to_residual_s"]
-    if not args.no_baselines:
-        out["baselines"] = baselines_leg(spec, args.max_cycles)
-        out["baselines"]["four_sided_64"] = four_sided_leg(args.max_cycles * 5)
-    if not args.no_batch:
-        out["batch"] = batch_leg()
-    if not args.no_learned:
-        out["learned"] = learned_leg(args.max_cycles)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(spec, 20.0)
+    legs = set() if args.legs == "none" else set(args.legs.split(","))
+    h = headline(args)
+    out = {"metric": METRIC, "value": h.pop("value"), "unit": "cell-moment updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": h.pop("ms_per_step"),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic", **h}
+    if "heated" in legs:
+        out["heated256_m8"] = heated_leg(args.max_cycles)
+    if "learned" in legs:
+        out["learned"] = learned_leg(args.learned_draws, args.max_cycles)
+    if "single" in legs:
+        out["single_cavity"] = single_leg(args.single_workload, args.max_cycles)
+    if "cpu" in legs:
+        out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
 

@@ -74,7 +74,9 @@ typedef struct {
   int32_t nx, ny;         /* finest grid; both divisible by 2^(levels-1) */
   double lx, ly;          /* domain size */
   int32_t M;              /* expansion order, 3 <= M <= 8 */
-  int32_t collision;      /* 0 = BGK (eq. (6)), 1 = Shakhov (eq. (8)) */
+  int32_t collision;      /* 0 = BGK (eq. (6)), 1 = Shakhov (eq. (8)), 2 = ES-BGK (eq. (7):
+                             Gaussian of covariance theta I + (1 - 1/Pr) sigma / rho; Sec. 4
+                             takes beta = Pr for it) */
   double Pr, Kn, omega, beta; /* nu = beta sqrt(pi/2) rho theta^(1-omega) / Kn, eq. (29) */
   int32_t order;          /* 1 or 2: spatial reconstruction, eq. (15) */
   int32_t limiter;        /* order 2 only: 0 = minmod, 1 = central slopes */
@@ -275,6 +277,11 @@ typedef struct {
                             on neighbouring columns (shorter latency); 0: waits first, then an
                             unsplit team (fewer registers, more teams per CU) */
   double block_ms;       /* last autotune: time of one s1-step block on level 0 */
+  int32_t kernel;        /* 0: cell-team sweep kernel (team_width wavefronts per cell, split);
+                            1: wavefront-per-cell sweep kernel (each wavefront updates the cells
+                            of its own units alone: longer latency per cell, many more cells in
+                            flight per CU; team_width and split are ignored).  Both give the
+                            same results bit for bit. */
 } nrxx_batch_tuning;
 
 /* Validates every problem as nrxx_create does, plus the shared fields; builds
@@ -286,9 +293,11 @@ int nrxx_batch_destroy(nrxx_batch *b);
 const char *nrxx_batch_last_error(const nrxx_batch *b);
 int nrxx_batch_groups(const nrxx_batch *b);
 int nrxx_batch_get_tuning(const nrxx_batch *b, int group, nrxx_batch_tuning *out);
-/* Sets team_width, grid and unit_order of a group (NRXX_EINVAL if invalid). */
+/* Sets kernel, team_width, split, grid and unit_order of a group (NRXX_EINVAL if
+ * invalid). */
 int nrxx_batch_set_tuning(nrxx_batch *b, int group, const nrxx_batch_tuning *t);
-/* Times every candidate (split x team width x grid {all resident, half} x unit order)
+/* Times every candidate (cell-team kernel: split x team width x grid {all
+ * resident, half} x unit order; wavefront-per-cell kernel: grid x unit order)
  * on one s1-step smoothing block of the finest level of `states`, keeps the
  * fastest per group, and restores `states` bit for bit. */
 int nrxx_batch_autotune(nrxx_batch *b, double *const *states);
@@ -316,6 +325,18 @@ int nrxx_batch_set_wait_limit(nrxx_batch *b, double seconds);
 /* Device time (ms) of the batch's V-cycles and the cell updates their sweeps
  * made since creation or the last reset. */
 int nrxx_batch_stats(nrxx_batch *b, double *ms_out, double *cell_updates_out, int reset);
+/* on = 1: record a HIP event pair on the group's stream around every sweep
+ * kernel launch enqueued directly (captured graphs carry no timing events:
+ * time with use_graph = 0); 0: off (default).  Autotuning is never timed. */
+int nrxx_batch_set_timing(nrxx_batch *b, int32_t on);
+/* Sweep-kernel statistics of one group while timing is on, since the last
+ * reset: summed launch durations (ms), launches, and the cell updates those
+ * launches made on the finest level and on coarse levels (problems masked
+ * off by convergence are not counted).  Groups run concurrently on their
+ * own streams, so durations of different groups overlap in time. */
+int nrxx_batch_kernel_stats(nrxx_batch *b, int32_t group, double *ms_out, double *launches_out,
+                            double *cell_updates_fine_out, double *cell_updates_coarse_out,
+                            int32_t reset);
 
 /* ---------------------------------------------------------------------------
  * Warm start from macroscopic fields, and the warm-start network.

@@ -84,6 +84,7 @@ def lib():
                                   ctypes.c_void_p]),
             "orc_euler_step": (c_int, [P, c_int, _dp, ctypes.POINTER(c_double)]),
             "orc_set_threads": (None, [c_int]),
+            "orc_set_vcycle_wavefront": (None, [c_int]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -96,6 +97,12 @@ def lib():
 
 def set_threads(n: int) -> None:
     lib().orc_set_threads(int(n))
+
+
+def set_vcycle_wavefront(on: bool) -> None:
+    """V-cycles sweep in anti-diagonal order (parallel over a diagonal's
+    cells) instead of the serial order; the result is bitwise the same."""
+    lib().orc_set_vcycle_wavefront(int(bool(on)))
 
 
 def _ptr(a):

@@ -826,13 +826,21 @@ int orc_correct(const orc_problem *P, int level_fine, double *fine, const double
 /* One step of the (levels-level) NMG iteration, Alg. 2, on `level`
  * (0 = finest here; the paper counts from the coarsest).  The coarsest
  * solver is exactly s3 fast-sweeping steps. */
+/* Sweep order used inside the V-cycle: 0 = serial order of Alg. 1, 1 = the
+ * anti-diagonal order (bitwise the same result; parallel over the cells of
+ * a diagonal with OpenMP). */
+static int g_vcycle_wavefront = 0;
+
+void orc_set_vcycle_wavefront(int on) { g_vcycle_wavefront = on ? 1 : 0; }
+
 int orc_vcycle(const orc_problem *P, int level, double *st, const double *rhs) {
-  if (level == P->levels - 1) return orc_sweep(P, level, st, rhs, 15, P->s3, 0);
+  const int wf = g_vcycle_wavefront;
+  if (level == P->levels - 1) return orc_sweep(P, level, st, rhs, 15, P->s3, wf);
   int nx, ny;
   orc_level_shape(P, level, &nx, &ny);
   int R = rlen(P);
   size_t nf = (size_t)nx * ny * R, nc = nf / 4;
-  if (orc_sweep(P, level, st, rhs, 15, P->s1, 0)) return -1;
+  if (orc_sweep(P, level, st, rhs, 15, P->s1, wf)) return -1;
   double *Rb = (double *)malloc(sizeof(double) * nf);
   double *fH = (double *)malloc(sizeof(double) * nc), *RH = (double *)malloc(sizeof(double) * nc);
   double *rH = (double *)malloc(sizeof(double) * nc), *fT = (double *)malloc(sizeof(double) * nc);
@@ -846,7 +854,7 @@ int orc_vcycle(const orc_problem *P, int level, double *st, const double *rhs) {
   }
   if (!rc) {
     orc_correct(P, level, st, fT, fH);
-    rc = orc_sweep(P, level, st, rhs, 15, P->s2, 0);
+    rc = orc_sweep(P, level, st, rhs, 15, P->s2, wf);
   }
   free(Rb); free(fH); free(RH); free(rH); free(fT);
   return rc;

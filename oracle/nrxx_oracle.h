@@ -80,6 +80,8 @@ int orc_solve(const orc_problem *P, double *st, double tol, int max_cycles, doub
               int *cycles, double *hist);
 int orc_euler_step(const orc_problem *P, int level, double *st, double *dt_used);
 void orc_set_threads(int n);
+/* 1: V-cycles sweep in anti-diagonal order (OpenMP), 0: serial order. */
+void orc_set_vcycle_wavefront(int on);
 
 #ifdef __cplusplus
 }

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnrxx.so")
 SOURCES = ["nrxx_kernels.hip", "nrxx_batch.hip", "nrxx_api.cpp", "nrxx_batch_api.cpp", "nrxx_mlp.hip",
-           "nrxx_noalloc.cpp"]
+           "nrxx_noalloc.cpp", "nrxx_wsweep.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -24,11 +24,18 @@ FLAGS = [
 ]
 
 
+# Per-file extra flags.  The wavefront-per-cell sweep keeps many cells in
+# flight per CU only while its register footprint stays small; machine-level
+# loop-invariant code motion hoists lane-dependent address arithmetic out of
+# its cell loops and roughly doubles that footprint, so it is off there.
+EXTRA = {"nrxx_wsweep.hip": ["-mllvm", "-disable-machine-licm"]}
+
+
 def build(verbose: bool = False) -> str:
     objs, procs = [], []
     for src in SOURCES:
         obj = os.path.join(CSRC, src + ".o")
-        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd.insert(1, "-xhip")
         if verbose:

@@ -401,7 +401,8 @@ bool validate_problem(const nrxx_problem &P, char *msg_buf, size_t cap) {
   const int f = 1 << (P.levels - 1);
   if (P.nx % f || P.ny % f) return bad(msg, "grid %d x %d not divisible by 2^(levels-1) = %d", P.nx, P.ny, f);
   if (P.nx / f < 2 || P.ny / f < 2) return bad(msg, "coarsest grid below 2 x 2");
-  if (P.collision != 0 && P.collision != 1) return bad(msg, "collision = %d", P.collision);
+  if (P.collision < 0 || P.collision > 2) return bad(msg, "collision = %d", P.collision);
+  if (P.collision == 2 && !(P.Pr > 0)) return bad(msg, "ES-BGK needs Pr > 0");
   if (P.order != 1 && P.order != 2) return bad(msg, "order = %d", P.order);
   if (P.limiter != 0 && P.limiter != 1) return bad(msg, "limiter = %d", P.limiter);
   if (!(P.lx > 0) || !(P.ly > 0) || !(P.Kn > 0) || !(P.cfl > 0) || !(P.beta > 0))

@@ -35,9 +35,20 @@ struct nrxx_batch {
     double *partial = nullptr;              // level-0 per-cell scalars
     std::vector<void *> owned;
     int nw = 0, grid = 0, major = 0, split = 1;
+    int kernel = 0;  // 0: cell-team sweep kernel, 1: wavefront-per-cell sweep kernel
     double tuned_ms = 0.0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // sweep-kernel timing (nrxx_batch_set_timing): an event pair around each
+    // eagerly enqueued sweep launch, with the level and the problems it served
+    struct Timed {
+      hipEvent_t a = nullptr, b = nullptr;
+      int k = 0, which = 0, nsw = 0;
+    };
+    std::vector<Timed> tl;
+    size_t tl_used = 0;
+    bool ran = false;       // work of this group was enqueued since the last harvest
+    double k_ms = 0.0, k_launches = 0.0, k_cells_fine = 0.0, k_cells_coarse = 0.0;
   };
   int n = 0, L = 0, s1 = 0, s2 = 0, s3 = 0, gamma = 1;
   hipStream_t stream = nullptr;
@@ -51,6 +62,8 @@ struct nrxx_batch {
   std::vector<double *> cur;    // level-0 state pointers in the tables
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double ms = 0.0, cells = 0.0;
+  int timing = 0;               // 1: time every sweep launch (nrxx_batch_kernel_stats)
+  std::vector<int> hact;        // active flags of the work being enqueued or replayed
   unsigned long long wait_ticks = 200000000ULL;  // bound of one cross-column wait: 2 s at 100 MHz
 };
 
@@ -149,9 +162,56 @@ int smooth(nrxx_batch *b, Group &G, int k, int nsteps, int which) {
     for (int q = 0; q < nsw; ++q) dirs |= (unsigned)((s0 + q) & 3) << (2 * q);
     BCHK(launch_bfill(G.cnt[k], G.cntsize[k], 0, G.stream));
     const int grid = std::max(1, std::min(G.grid, nsw * U));
-    BCHK(launch_bsweep(G.M, G.order, G.nw, G.split, grid, G.dtab[k], G.units[G.major][which][k], U, nsw,
-                       dirs, G.cnt[k], G.cols[k], b->active, b->derr, b->dabort, b->wait_ticks,
-                       G.stream));
+    Group::Timed *t = nullptr;
+    if (b->timing) {
+      if (G.tl_used == G.tl.size()) {
+        G.tl.emplace_back();
+        BCHK(hipEventCreate(&G.tl.back().a));
+        BCHK(hipEventCreate(&G.tl.back().b));
+      }
+      t = &G.tl[G.tl_used++];
+      G.ran = true;
+      t->k = k;
+      t->which = which;
+      t->nsw = nsw;
+      BCHK(hipEventRecord(t->a, G.stream));
+    }
+    if (G.kernel == 1)
+      BCHK(launch_wsweep(G.M, G.order, grid, G.dtab[k], G.units[G.major][which][k], U, nsw, dirs,
+                         G.cnt[k], G.cols[k], b->active, b->derr, b->dabort, b->wait_ticks,
+                         G.stream));
+    else
+      BCHK(launch_bsweep(G.M, G.order, G.nw, G.split, grid, G.dtab[k], G.units[G.major][which][k], U,
+                         nsw, dirs, G.cnt[k], G.cols[k], b->active, b->derr, b->dabort,
+                         b->wait_ticks, G.stream));
+    if (t) BCHK(hipEventRecord(t->b, G.stream));
+  }
+  return NRXX_OK;
+}
+
+// Adds the recorded sweep launches of every group (work finished: called
+// after a synchronisation) to the kernel statistics; cell updates count the
+// problems active in that work (b->hact); the lists are then emptied.
+int harvest_timing(nrxx_batch *b) {
+  if (!b->timing) return NRXX_OK;
+  for (auto &G : b->g) {
+    if (!G.ran) continue;
+    G.ran = false;
+    for (size_t q = 0; q < G.tl_used; ++q) {
+      const Group::Timed &t = G.tl[q];
+      float ms = 0.f;
+      BCHK(hipEventElapsedTime(&ms, t.a, t.b));
+      double cells = 0.0;
+      for (size_t s = 0; s < G.inst.size(); ++s) {
+        const BLevel &e = G.htab[t.k][s];
+        if (e.ncell > 0 && e.cont == (t.which == 0 ? 1 : 0) && b->hact[e.inst]) cells += e.ncell;
+      }
+      if (cells == 0.0) continue;  // every problem of the launch was masked off
+      G.k_ms += ms;
+      G.k_launches += 1.0;
+      (t.k == 0 ? G.k_cells_fine : G.k_cells_coarse) += cells * t.nsw;
+    }
+    G.tl_used = 0;
   }
   return NRXX_OK;
 }
@@ -211,8 +271,15 @@ void drop_graph(Group &G) {
 
 int capture(nrxx_batch *b, Group &G) {
   drop_graph(G);
+  G.tl_used = 0;
+  // HIP reports no elapsed time between events recorded by graph nodes, so
+  // captured cycles carry no timing events (timing covers eager work only)
+  const int timing = b->timing;
+  b->timing = 0;
   BCHK(hipStreamBeginCapture(G.stream, hipStreamCaptureModeThreadLocal));
   int rc = cycle_enqueue(b, G, true);
+  b->timing = timing;
+  G.ran = false;  // captured, not run
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(G.stream, &graph);
   if (rc) {
@@ -419,6 +486,10 @@ int nrxx_batch_destroy(nrxx_batch *b) {
   for (auto &G : b->g) {
     if (G.stream) (void)hipStreamSynchronize(G.stream);
     drop_graph(G);
+    for (auto &t : G.tl) {
+      if (t.a) (void)hipEventDestroy(t.a);
+      if (t.b) (void)hipEventDestroy(t.b);
+    }
     for (void *p : G.owned) (void)hipFree(p);
     if (G.done) (void)hipEventDestroy(G.done);
     if (G.stream) (void)hipStreamDestroy(G.stream);
@@ -451,6 +522,7 @@ int nrxx_batch_get_tuning(const nrxx_batch *b, int group, nrxx_batch_tuning *t) 
   t->unit_order = G.major;
   t->split = G.split;
   t->block_ms = G.tuned_ms;
+  t->kernel = G.kernel;
   return NRXX_OK;
 }
 
@@ -458,12 +530,16 @@ int nrxx_batch_set_tuning(nrxx_batch *b, int group, const nrxx_batch_tuning *t) 
   if (!b) return NRXX_EINVAL;
   if (!t || group < 0 || group >= (int)b->g.size()) return bfail(b, NRXX_EINVAL, "bad group");
   Group &G = b->g[group];
-  if (!batch_width_ok(G.M, t->team_width)) return bfail(b, NRXX_EINVAL, "team width %d", t->team_width);
+  if (t->kernel != 0 && t->kernel != 1) return bfail(b, NRXX_EINVAL, "kernel %d", t->kernel);
+  if (t->kernel == 0 && !batch_width_ok(G.M, t->team_width))
+    return bfail(b, NRXX_EINVAL, "team width %d", t->team_width);
   if (t->grid < 1 || (t->unit_order != 0 && t->unit_order != 1) || (t->split != 0 && t->split != 1))
     return bfail(b, NRXX_EINVAL, "bad grid, unit order or split");
-  if (G.nw != t->team_width || G.grid != t->grid || G.major != t->unit_order || G.split != t->split)
+  if (G.kernel != t->kernel || G.nw != t->team_width || G.grid != t->grid ||
+      G.major != t->unit_order || G.split != t->split)
     drop_graph(G);
-  G.nw = t->team_width;
+  G.kernel = t->kernel;
+  if (t->kernel == 0) G.nw = t->team_width;
   G.grid = t->grid;
   G.major = t->unit_order;
   G.split = t->split;
@@ -506,12 +582,14 @@ int nrxx_batch_sweep(nrxx_batch *b, double *const *states, int nsteps) {
   if (rc) return rc;
   rc = set_all_active(b, 1);
   if (rc) return rc;
+  b->hact.assign(b->n, 1);
   rc = on_groups(b, [&](Group &G) {
     int r = smooth(b, G, 0, nsteps, 0);
     return r ? r : smooth(b, G, 0, nsteps, 1);
   });
   if (rc) return rc;
-  return fetch(b);
+  rc = fetch(b);
+  return rc ? rc : harvest_timing(b);
 }
 
 int nrxx_batch_vcycle(nrxx_batch *b, double *const *states, double *norms_out) {
@@ -520,9 +598,12 @@ int nrxx_batch_vcycle(nrxx_batch *b, double *const *states, double *norms_out) {
   if (rc) return rc;
   rc = set_all_active(b, 1);
   if (rc) return rc;
+  b->hact.assign(b->n, 1);
   rc = on_groups(b, [&](Group &G) { return cycle_enqueue(b, G, false); });
   if (rc) return rc;
   rc = fetch(b);
+  if (rc) return rc;
+  rc = harvest_timing(b);
   if (rc) return rc;
   if (norms_out) memcpy(norms_out, b->h_dbl, sizeof(double) * b->n);
   return NRXX_OK;
@@ -562,6 +643,7 @@ int nrxx_batch_solve(nrxx_batch *b, double *const *states, double tol, int32_t m
     if (!nact) break;
     for (int i = 0; i < b->n; ++i)
       if (act[i]) b->cells += cycle_cells(b, i);
+    b->hact = act;
     BCHK(hipEventRecord(b->ev1, b->stream));
     rc = on_groups(b, [&](Group &G) {
       bool any = false;
@@ -573,6 +655,8 @@ int nrxx_batch_solve(nrxx_batch *b, double *const *states, double tol, int32_t m
     if (rc) return rc;
     BCHK(hipEventRecord(b->ev0, b->stream));
     rc = fetch(b);
+    if (rc) return rc;
+    rc = harvest_timing(b);
     if (rc) return rc;
     float ms = 0.f;
     BCHK(hipEventElapsedTime(&ms, b->ev1, b->ev0));
@@ -598,6 +682,13 @@ int nrxx_batch_autotune(nrxx_batch *b, double *const *states) {
   hipEvent_t t0, t1;
   BCHK(hipEventCreate(&t0));
   BCHK(hipEventCreate(&t1));
+  // the candidates' sweeps are not part of the kernel statistics
+  struct Untimed {
+    nrxx_batch *b;
+    int was;
+    ~Untimed() { b->timing = was; }
+  } untimed{b, b->timing};
+  b->timing = 0;
   for (auto &G : b->g) {
     // back up the group's finest-level states
     std::vector<double *> bak(G.inst.size(), nullptr);
@@ -615,53 +706,64 @@ int nrxx_batch_autotune(nrxx_batch *b, double *const *states) {
       }
       return hipStreamSynchronize(b->stream) == hipSuccess;
     };
+    // candidates: (kernel, team width, split, grid, unit order)
+    struct Cand {
+      int kernel, nw, split, grid, major;
+    };
+    std::vector<Cand> cands;
     const int widths[4] = {8, 4, 2, 1};
+    for (int sp = 1; sp >= 0; --sp)
+      for (int wi = 0; wi < 4; ++wi) {
+        if (!batch_width_ok(G.M, widths[wi])) continue;
+        const int res = bsweep_resident(G.M, G.order, widths[wi], sp);
+        if (res < 1) continue;
+        for (int gr : {res, std::max(1, res / 2)})
+          for (int m = 0; m < 2; ++m) cands.push_back({0, widths[wi], sp, gr, m});
+      }
+    {
+      const int res = wsweep_resident(G.M, G.order);
+      if (res >= 1)
+        for (int gr : {res, std::max(1, res / 2)})
+          for (int m = 0; m < 2; ++m) cands.push_back({1, G.nw, G.split, gr, m});
+    }
     double best = 1e300;
-    int bw = G.nw, bg = G.grid, bm = G.major, bs = G.split;
-    for (int sp = 1; sp >= 0 && ok; --sp)
-    for (int wi = 0; wi < 4 && ok; ++wi) {
-      if (!batch_width_ok(G.M, widths[wi])) continue;
-      const int res = bsweep_resident(G.M, G.order, widths[wi], sp);
-      if (res < 1) continue;
-      const int grids[2] = {res, std::max(1, res / 2)};
-      for (int gi = 0; gi < 2 && ok; ++gi)
-        for (int m = 0; m < 2 && ok; ++m) {
-          G.nw = widths[wi];
-          G.grid = grids[gi];
-          G.major = m;
-          G.split = sp;
-          float ms = 0.f;
-          for (int rep = 0; rep < 2 && ok; ++rep) {  // the first run loads the code object
-            ok = restore();
-            if (!ok) break;
-            BCHK(hipEventRecord(t0, G.stream));
-            rc = smooth(b, G, 0, std::max(1, b->s1), 0);
-            if (rc) return rc;
-            rc = smooth(b, G, 0, std::max(1, b->s1), 1);
-            if (rc) return rc;
-            BCHK(hipEventRecord(t1, G.stream));
-            BCHK(hipEventSynchronize(t1));
-            BCHK(hipEventElapsedTime(&ms, t0, t1));
-          }
-          rc = fetch(b);
-          if (rc) return rc;
-          if (ms < best) {
-            best = ms;
-            bw = G.nw;
-            bg = G.grid;
-            bm = G.major;
-            bs = G.split;
-          }
-        }
+    Cand keep{G.kernel, G.nw, G.split, G.grid, G.major};
+    for (const Cand &cd : cands) {
+      if (!ok) break;
+      G.kernel = cd.kernel;
+      G.nw = cd.nw;
+      G.split = cd.split;
+      G.grid = cd.grid;
+      G.major = cd.major;
+      float ms = 0.f;
+      for (int rep = 0; rep < 2 && ok; ++rep) {  // the first run loads the code object
+        ok = restore();
+        if (!ok) break;
+        BCHK(hipEventRecord(t0, G.stream));
+        rc = smooth(b, G, 0, std::max(1, b->s1), 0);
+        if (rc) return rc;
+        rc = smooth(b, G, 0, std::max(1, b->s1), 1);
+        if (rc) return rc;
+        BCHK(hipEventRecord(t1, G.stream));
+        BCHK(hipEventSynchronize(t1));
+        BCHK(hipEventElapsedTime(&ms, t0, t1));
+      }
+      rc = fetch(b);
+      if (rc) return rc;
+      if (ms < best) {
+        best = ms;
+        keep = cd;
+      }
     }
     if (ok) ok = restore();
     for (double *p : bak)
       if (p) (void)hipFree(p);
     if (!ok) return bfail(b, NRXX_EHIP, "autotune: copy or allocation failed");
-    G.nw = bw;
-    G.grid = bg;
-    G.major = bm;
-    G.split = bs;
+    G.kernel = keep.kernel;
+    G.nw = keep.nw;
+    G.split = keep.split;
+    G.grid = keep.grid;
+    G.major = keep.major;
     G.tuned_ms = best;
     drop_graph(G);
   }
@@ -675,6 +777,31 @@ int nrxx_batch_set_wait_limit(nrxx_batch *b, double seconds) {
   if (!(seconds >= 1e-8) || seconds > 3600.0) return bfail(b, NRXX_EINVAL, "wait limit %g s", seconds);
   b->wait_ticks = (unsigned long long)(seconds * 1e8);
   for (auto &G : b->g) drop_graph(G);  // captured cycles hold the old limit
+  return NRXX_OK;
+}
+
+int nrxx_batch_set_timing(nrxx_batch *b, int32_t on) {
+  if (!b) return NRXX_EINVAL;
+  if (on != 0 && on != 1) return bfail(b, NRXX_EINVAL, "timing must be 0 or 1");
+  if (b->timing != on)
+    for (auto &G : b->g) {
+      drop_graph(G);  // re-captured with (or without) the event pairs
+      G.tl_used = 0;
+    }
+  b->timing = on;
+  return NRXX_OK;
+}
+
+int nrxx_batch_kernel_stats(nrxx_batch *b, int32_t group, double *ms_out, double *launches_out,
+                            double *cells_fine_out, double *cells_coarse_out, int32_t reset) {
+  if (!b) return NRXX_EINVAL;
+  if (group < 0 || group >= (int)b->g.size()) return bfail(b, NRXX_EINVAL, "bad group");
+  Group &G = b->g[group];
+  if (ms_out) *ms_out = G.k_ms;
+  if (launches_out) *launches_out = G.k_launches;
+  if (cells_fine_out) *cells_fine_out = G.k_cells_fine;
+  if (cells_coarse_out) *cells_coarse_out = G.k_cells_coarse;
+  if (reset) G.k_ms = G.k_launches = G.k_cells_fine = G.k_cells_coarse = 0.0;
   return NRXX_OK;
 }
 

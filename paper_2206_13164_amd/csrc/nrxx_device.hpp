@@ -121,6 +121,7 @@ struct G {
   static constexpr int E1 = 1, E2 = D1, XX = 2, YY = 2 * D1, ZZ = D2;
   static constexpr int X3 = 3, X1Y2 = 1 + 2 * D1, X1Z2 = 1 + D2;
   static constexpr int Y3 = 3 * D1, X2Y1 = 2 + D1, Y1Z2 = D1 + D2;
+  static constexpr int XY = 1 + D1;
 };
 
 // LDS layout (in doubles) of a cell team of NW wavefronts (the last one also
@@ -355,6 +356,33 @@ __device__ __forceinline__ Real regul(int D, const Real *fL, const Real *fR, Rea
   if (b2 >= 2) acc += Real(0.5) * (Real(0.5) * (fL[base - g::D2] + fR[base - g::D2])) * dth;
   const int bd = D == 0 ? S.a1[r] : S.a2[r];
   return (bd + 1) * acc;
+}
+
+// ES-BGK equilibrium of eq. (7) in the cell's own basis [u, th]: the
+// Gaussian of covariance Lambda = th I + B, B = (1 - 1/Pr) sigma / rho, has
+// the coefficients f^E_alpha = rho [t^alpha] exp(t^T B t / 2) (the generating
+// function of the Hermite polynomials; the powers of th cancel).  In the
+// plane flow sigma_13 = sigma_23 = 0, so the series factorises:
+// [t1^a1 t2^a2] exp(B11 t1^2 / 2 + B12 t1 t2 + B22 t2^2 / 2) =
+//   sum_k B12^k / k! (B11 / 2)^i1 / i1! (B22 / 2)^i2 / i2!, i_d = (a_d - k) / 2,
+// times [t3^2m] exp(B33 t3^2 / 2) = (B33 / 2)^m / m!.
+template <typename Real>
+__device__ __forceinline__ Real esbgk_coef(int a1, int a2, int m, Real rho, Real b11, Real b12,
+                                           Real b22, Real b33) {
+  if ((a1 ^ a2) & 1) return Real(0.0);
+  const Real h11 = Real(0.5) * b11, h22 = Real(0.5) * b22, h33 = Real(0.5) * b33;
+  Real z = Real(1.0);
+  for (int q = 1; q <= m; ++q) z = z * h33 / Real(q);
+  const int kmax = a1 < a2 ? a1 : a2;
+  Real acc = Real(0.0);
+  for (int k = a1 & 1; k <= kmax; k += 2) {
+    Real t = Real(1.0);
+    for (int q = 1; q <= k; ++q) t = t * b12 / Real(q);
+    for (int q = 1; q <= (a1 - k) / 2; ++q) t = t * h11 / Real(q);
+    for (int q = 1; q <= (a2 - k) / 2; ++q) t = t * h22 / Real(q);
+    acc += t;
+  }
+  return rho * acc * z;
 }
 
 template <typename Real>
@@ -818,7 +846,8 @@ __device__ bool cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
     const Real rho = bC[0];
     const Real nu = sc[L::SNU];
     Real T[g::SL];
-    // collision Q = nu (f^E - f), eq. (5), (29); Shakhov f^E from eq. (8)
+    // collision Q = nu (f^E - f), eq. (5), (29); Shakhov f^E from eq. (8),
+    // ES-BGK f^E from eq. (7)
     Real c1 = Real(0.0), c2 = Real(0.0);
     if (A.collision == 1) {
       const Real q1 = Real(2.0) * bC[g::X3] + bC[g::X3] + bC[g::X1Y2] + bC[g::X1Z2];
@@ -826,12 +855,22 @@ __device__ bool cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
       c1 = (Real(1.0) - Real(A.Pr)) * q1 * Real(0.2);
       c2 = (Real(1.0) - Real(A.Pr)) * q2 * Real(0.2);
     }
+    Real b11 = Real(0.0), b12 = Real(0.0), b22 = Real(0.0), b33 = Real(0.0);
+    if (A.collision == 2) {
+      // B = (1 - 1/Pr) sigma / rho, sigma_ij = (1 + delta_ij) f_{e_i+e_j}
+      const Real kb = (Real(1.0) - Real(1.0) / Real(A.Pr)) / rho;
+      b11 = kb * (Real(2.0) * bC[g::XX]);
+      b12 = kb * bC[g::XY];
+      b22 = kb * (Real(2.0) * bC[g::YY]);
+      b33 = kb * (Real(2.0) * bC[g::ZZ]);
+    }
 #pragma unroll
     for (int r = 0; r < g::SL; ++r) {
       const int ca = S.ca[r];
       Real fE = ca == 0 ? rho : Real(0.0);
       if (ca == g::X3 || ca == g::X1Y2 || ca == g::X1Z2) fE += c1;
       if (ca == g::Y3 || ca == g::X2Y1 || ca == g::Y1Z2) fE += c2;
+      if (A.collision == 2) fE = esbgk_coef<Real>(S.a1[r], S.a2[r], S.m[r], rho, b11, b12, b22, b33);
       T[r] = S.ok[r] ? nu * (fE - c.f[r]) : Real(0.0);
     }
     put_slots<Real, M>(lds + L::T + L::T_Q * g::SLOT, lane, T);

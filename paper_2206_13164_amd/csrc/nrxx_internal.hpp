@@ -125,6 +125,14 @@ hipError_t launch_bsweep32(int M, int order, int nw, int grid, const BLevel *tab
                            const int *active, int *err, int *abort_flag, unsigned long long limit,
                            hipStream_t s, float *st, const float *rhs);
 int bsweep_resident(int M, int order, int nw, int split);
+// The wavefront-per-cell form of the same work-queue sweep (nrxx_wsweep.hip):
+// same units, order, counters and waits; every wavefront of a workgroup
+// takes its own units.  FP64 only.
+hipError_t launch_wsweep(int M, int order, int grid, const BLevel *tab, const int *units, int U,
+                         int nsweep, unsigned dirs, int *queue, int cstride, const int *active,
+                         int *err, int *abort_flag, unsigned long long limit, hipStream_t s);
+int wsweep_resident(int M, int order);  // workgroups resident at once (0 if unknown)
+int wsweep_wavefronts_per_group();
 int bsweep_resident32(int M, int order, int nw);
 // role 0: Rbar = rhs - R(st); 1: rhs = R(fbar) + RH; 2: partial = weighted squares
 hipError_t launch_bresidual(int M, int order, int ncell, const BLevel *tab, int nslot,

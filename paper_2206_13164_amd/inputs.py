@@ -59,6 +59,10 @@ WORKLOADS = {
     # coarsest grid
     "paper_table1_32": dict(nx=32, ny=32, M=5, collision=1, Pr=2.0 / 3.0, Kn=0.1, order=1,
                             wall_u=[0.0, 0.0, 0.2097, 0.0], levels=3, tol=1e-8),
+    # the ES-BGK model (eq. (7)) on the same single lid (Table 4 setup):
+    # Pr 2/3 and beta = Pr in the collision frequency (Sec. 4), 64x64, M = 5
+    "esbgk64_m5_kn01": dict(nx=64, ny=64, M=5, collision=2, Pr=2.0 / 3.0, beta=2.0 / 3.0, Kn=0.1,
+                            order=1, wall_u=[0.0, 0.0, 0.2097, 0.0], levels=4, tol=1e-8),
     # four-sided lid-driven cavity with anti-parallel wall motion (Sec. 4.2):
     # top moves right and the right wall up at U_W (50 m/s at 273 K, 0.2097),
     # bottom and left walls the opposite way; Shakhov, Kn 0.777, M = 5, 1st

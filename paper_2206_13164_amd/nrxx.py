@@ -40,7 +40,8 @@ class Problem(ctypes.Structure):
 
 class BatchTuning(ctypes.Structure):
     _fields_ = [("M", c_int), ("order", c_int), ("problems", c_int), ("team_width", c_int),
-                ("grid", c_int), ("unit_order", c_int), ("split", c_int), ("block_ms", c_double)]
+                ("grid", c_int), ("unit_order", c_int), ("split", c_int), ("block_ms", c_double),
+                ("kernel", c_int)]
 
 
 _PP = ctypes.POINTER(c_void_p)
@@ -80,6 +81,10 @@ EXPORTS = {
     "nrxx_batch_vcycle": (c_int, [c_void_p, _PP, c_void_p]),
     "nrxx_batch_solve": (c_int, [c_void_p, _PP, c_double, c_int, c_int, c_void_p, c_void_p, c_void_p]),
     "nrxx_batch_stats": (c_int, [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double), c_int]),
+    "nrxx_batch_set_timing": (c_int, [c_void_p, c_int]),
+    "nrxx_batch_kernel_stats": (c_int, [c_void_p, c_int, ctypes.POINTER(c_double),
+                                        ctypes.POINTER(c_double), ctypes.POINTER(c_double),
+                                        ctypes.POINTER(c_double), c_int]),
     "nrxx_set_wait_limit": (c_int, [c_void_p, c_double]),
     "nrxx_batch_set_wait_limit": (c_int, [c_void_p, c_double]),
     "nrxx_init_fields": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int]),
@@ -362,9 +367,10 @@ class Batch:
         self._chk(load().nrxx_batch_get_tuning(self.h, group, ctypes.byref(t)))
         return {k: getattr(t, k) for k, _ in BatchTuning._fields_}
 
-    def set_tuning(self, group, team_width, grid, unit_order, split=1):
+    def set_tuning(self, group, team_width, grid, unit_order, split=1, kernel=0):
         t = BatchTuning()
         t.team_width, t.grid, t.unit_order, t.split = team_width, grid, unit_order, split
+        t.kernel = kernel
         self._chk(load().nrxx_batch_set_tuning(self.h, group, ctypes.byref(t)))
 
     def autotune(self, states):
@@ -398,6 +404,17 @@ class Batch:
 
     def set_wait_limit(self, seconds):
         self._chk(load().nrxx_batch_set_wait_limit(self.h, float(seconds)))
+
+    def set_timing(self, on=True):
+        self._chk(load().nrxx_batch_set_timing(self.h, int(bool(on))))
+
+    def kernel_stats(self, group, reset=False):
+        """(ms, launches, fine cell updates, coarse cell updates) of the
+        group's sweep launches while timing is on."""
+        v = [c_double() for _ in range(4)]
+        self._chk(load().nrxx_batch_kernel_stats(self.h, group, *[ctypes.byref(x) for x in v],
+                                                 int(reset)))
+        return tuple(x.value for x in v)
 
     def stats(self, reset=False):
         ms, cells = c_double(), c_double()

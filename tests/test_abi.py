@@ -39,8 +39,9 @@ def test_record_stride():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(M=2), dict(M=9), dict(nx=31), dict(levels=6), dict(order=3), dict(collision=2),
+    dict(M=2), dict(M=9), dict(nx=31), dict(levels=6), dict(order=3), dict(collision=-1),
     dict(Kn=0.0), dict(wall_theta=[1.0, 0.0, 1.0, 1.0]), dict(gamma=0), dict(precision=7),
+    dict(collision=3), dict(collision=2, Pr=0.0),
     dict(limiter=5), dict(nx=4, ny=4, levels=3), dict(schedule=4),
 ])
 def test_create_rejects_invalid_problems_before_touching_the_gpu(bad):

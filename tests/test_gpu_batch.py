@@ -23,6 +23,8 @@ def mixed_specs(levels=(2, 2, 2, 2, 2)):
         I.spec(None, M=8, collision=1, Pr=2.0 / 3.0, order=2, limiter=1, nx=12, ny=12, Kn=0.2,
                levels=L[3], **base),
         I.spec(None, M=3, collision=1, Pr=2.0 / 3.0, order=1, nx=8, ny=24, Kn=1.0, levels=L[4], **base),
+        I.spec(None, M=5, collision=2, Pr=2.0 / 3.0, beta=2.0 / 3.0, order=2, limiter=1, nx=12,
+               ny=16, Kn=0.4, levels=L[5] if len(L) > 5 else 2, **base),
     ]
 
 
@@ -72,14 +74,42 @@ def test_batch_sweep_bitwise_equals_single_problem_sweeps():
                         assert bool((st[k] == want[k]).all()), (k, split, width, grid, order)
 
 
+def test_wavefront_kernel_sweeps_bitwise_equal_single_problem_sweeps():
+    # the wavefront-per-cell sweep kernel gives the cell team's results bit
+    # for bit, for any grid (also far fewer wavefronts than columns) and
+    # either unit order
+    require_gpu()
+    from paper_2206_13164_amd import nrxx as N
+    specs = mixed_specs((2, 2, 3, 1, 2))
+    b = N.Batch(specs)
+    st0 = random_states(b, specs, 33)
+    want = single_results(specs, st0, lambda c, d: c.sweep(d, nsteps=2))
+    full = [b.tuning(g)["grid"] for g in range(b.groups())]
+    for grid in (None, 1, 3):
+        for order in (0, 1):
+            for g in range(b.groups()):
+                t = b.tuning(g)
+                b.set_tuning(g, t["team_width"], grid or full[g], order, 1, kernel=1)
+                assert b.tuning(g)["kernel"] == 1
+            print(f"wavefront kernel: grid {grid} order {order}", flush=True)
+            st = [x.clone() for x in st0]
+            b.sweep(st, nsteps=2)
+            for k in range(len(specs)):
+                assert bool((st[k] == want[k]).all()), (k, grid, order)
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
 @pytest.mark.parametrize("levels", [(2, 2, 2, 2, 2), (3, 3, 2, 1, 3)])
-def test_batch_vcycle_bitwise_equals_single_problem_vcycles(levels):
+def test_batch_vcycle_bitwise_equals_single_problem_vcycles(levels, kernel):
     # problems of one batch may have different level counts (each takes its
     # coarsest steps on its own coarsest level)
     require_gpu()
     from paper_2206_13164_amd import nrxx as N
     specs = mixed_specs(levels)
     b = N.Batch(specs)
+    for g in range(b.groups()):
+        t = b.tuning(g)
+        b.set_tuning(g, t["team_width"], t["grid"], t["unit_order"], t["split"], kernel=kernel)
     st = [x.clone() for x in random_states(b, specs, 41)]
     want_norms = []
 
@@ -156,11 +186,17 @@ def test_batch_autotune_restores_states_and_keeps_results():
         assert bool((st[k] == want[k]).all()), k
 
 
-def test_batch_wait_timeout_is_reported_and_the_batch_recovers():
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_batch_wait_timeout_is_reported_and_the_batch_recovers(kernel):
+    # the wait bound is forced from the host (a 10 ns limit): every
+    # wavefront gives up, the kernel ends, the error is reported
     require_gpu()
     from paper_2206_13164_amd import nrxx as N
     specs = mixed_specs()
     b = N.Batch(specs)
+    for g in range(b.groups()):
+        t = b.tuning(g)
+        b.set_tuning(g, t["team_width"], t["grid"], t["unit_order"], t["split"], kernel=kernel)
     st0 = random_states(b, specs, 61)
     st = [x.clone() for x in st0]
     b.set_wait_limit(1e-8)

@@ -13,6 +13,8 @@ pytestmark = pytest.mark.gpu
 CASES = [
     (3, 0, 1, 0), (3, 1, 2, 0), (4, 1, 2, 1), (5, 1, 2, 0), (5, 0, 1, 0),
     (6, 1, 1, 0), (7, 1, 2, 0), (8, 1, 2, 0), (8, 1, 1, 0),
+    # ES-BGK (collision 2)
+    (3, 2, 1, 0), (5, 2, 2, 1), (8, 2, 2, 0),
 ]
 
 

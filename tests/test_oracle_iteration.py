@@ -29,6 +29,27 @@ def test_wavefront_order_equals_serial_order(orc, order, limiter):
         assert np.array_equal(a, b), mask
 
 
+def test_vcycle_in_wavefront_order_equals_serial_vcycle(orc):
+    # the CPU baseline's parallel mode: V-cycles whose sweeps run over
+    # anti-diagonals on several threads give the serial V-cycle bit for bit
+    s = I.spec(None, M=3, collision=1, Pr=2 / 3, nx=16, ny=16, order=2, limiter=1, levels=3,
+               wall_u=[0.0, 0.0, 0.3, 0.0])
+    P = orc.problem(s)
+    a = I.maxwellian_state(s)
+    b = a.copy()
+    for _ in range(2):
+        orc.vcycle(P, a)
+    orc.set_threads(4)
+    orc.set_vcycle_wavefront(True)
+    try:
+        for _ in range(2):
+            orc.vcycle(P, b)
+    finally:
+        orc.set_vcycle_wavefront(False)
+        orc.set_threads(1)
+    assert np.array_equal(a, b)
+
+
 def test_sweep_moves_towards_steady_state(orc):
     s = I.spec("lid32_bgk_m3", nx=16, ny=16)
     P = orc.problem(s)
