@@ -73,7 +73,8 @@ typedef enum {
 typedef struct {
   int32_t nx, ny;         /* finest grid; both divisible by 2^(levels-1) */
   double lx, ly;          /* domain size */
-  int32_t M;              /* expansion order, 3 <= M <= 8 */
+  int32_t M;              /* expansion order, 3 <= M <= 10; M > 8 runs FP64 (precision 0)
+                             with the work-queue schedule (0 or 3) only */
   int32_t collision;      /* 0 = BGK (eq. (6)), 1 = Shakhov (eq. (8)), 2 = ES-BGK (eq. (7):
                              Gaussian of covariance theta I + (1 - 1/Pr) sigma / rho; Sec. 4
                              takes beta = Pr for it) */
@@ -282,6 +283,9 @@ typedef struct {
                             of its own units alone: longer latency per cell, many more cells in
                             flight per CU; team_width and split are ignored).  Both give the
                             same results bit for bit. */
+  int32_t rows_per_sync; /* kernel 1: rows of a column updated per set of waits on neighbouring
+                            columns and per acquire/release (>= 1; larger: fewer cache
+                            invalidations, later start of the downstream column) */
 } nrxx_batch_tuning;
 
 /* Validates every problem as nrxx_create does, plus the shared fields; builds
@@ -297,7 +301,8 @@ int nrxx_batch_get_tuning(const nrxx_batch *b, int group, nrxx_batch_tuning *out
  * invalid). */
 int nrxx_batch_set_tuning(nrxx_batch *b, int group, const nrxx_batch_tuning *t);
 /* Times every candidate (cell-team kernel: split x team width x grid {all
- * resident, half} x unit order; wavefront-per-cell kernel: grid x unit order)
+ * resident, half} x unit order; wavefront-per-cell kernel with rows_per_sync 1:
+ * grid x unit order)
  * on one s1-step smoothing block of the finest level of `states`, keeps the
  * fastest per group, and restores `states` bit for bit. */
 int nrxx_batch_autotune(nrxx_batch *b, double *const *states);

@@ -179,10 +179,16 @@ int queue_sweeps(nrxx_ctx *c, int level, Real *st, const Real *rhs, const std::v
     CHK(launch_bfill(c->qcnt[level], ncnt, 0, c->stream));
     const int full = sizeof(Real) == 8 ? c->qgrid : c->qgrid32;
     const int grid = std::max(1, std::min(full, nsw * A.nx));
-    if constexpr (sizeof(Real) == 8)
-      CHK(launch_bsweep(c->M, A.order, c->qnw, 1, grid, c->qtab[level], c->qunits[level], A.nx, nsw,
-                        bits, c->qcnt[level], A.nx, c->qactive, c->derr, c->dabort, c->wait_ticks,
-                        c->stream, st, rhs));
+    if constexpr (sizeof(Real) == 8) {
+      if (c->M > MTEAM)  // one wavefront per cell past the cell team's largest M
+        CHK(launch_wsweep(c->M, A.order, grid, c->qtab[level], c->qunits[level], A.nx, nsw, bits,
+                          c->qcnt[level], A.nx, c->qactive, c->derr, c->dabort, c->wait_ticks, 1,
+                          c->stream, st, rhs));
+      else
+        CHK(launch_bsweep(c->M, A.order, c->qnw, 1, grid, c->qtab[level], c->qunits[level], A.nx,
+                          nsw, bits, c->qcnt[level], A.nx, c->qactive, c->derr, c->dabort,
+                          c->wait_ticks, c->stream, st, rhs));
+    }
     else
       CHK(launch_bsweep32(c->M, A.order, c->qnw, grid, c->qtab[level], c->qunits[level], A.nx, nsw,
                           bits, c->qcnt[level], A.nx, c->qactive, c->derr, c->dabort, c->wait_ticks,
@@ -414,6 +420,10 @@ bool validate_problem(const nrxx_problem &P, char *msg_buf, size_t cap) {
   if (P.precision != 0 && P.precision != 1)
     return bad(msg, "precision = %d not supported", P.precision);
   if (P.schedule < 0 || P.schedule > 3) return bad(msg, "schedule = %d", P.schedule);
+  if (P.M > MTEAM && P.precision != 0)
+    return bad(msg, "M = %d > %d needs precision 0 (FP64 sweeps)", P.M, MTEAM);
+  if (P.M > MTEAM && P.schedule != 0 && P.schedule != 3)
+    return bad(msg, "M = %d > %d needs the work-queue schedule (0 or 3)", P.M, MTEAM);
   if ((long long)P.nx * P.ny > (1LL << 26)) return bad(msg, "grid too large");
 
   return true;
@@ -535,7 +545,7 @@ int nrxx_create(const nrxx_problem *p, void *hip_stream, nrxx_ctx **out) {
   // all resident at once; 2) or one launch per anti-diagonal (1)
   if (P.schedule == 0 || P.schedule == 3) {
     c->qnw = P.M <= 5 ? 8 : 2;
-    c->qgrid = bsweep_resident(P.M, P.order, c->qnw, 1);
+    c->qgrid = P.M > MTEAM ? wsweep_resident(P.M, P.order) : bsweep_resident(P.M, P.order, c->qnw, 1);
     c->qgrid32 = P.precision == 1 ? bsweep_resident32(P.M, P.order, c->qnw) : 1;
     bool qok = c->qgrid >= 1 && c->qgrid32 >= 1 &&
                hipMalloc((void **)&c->qactive, sizeof(int)) == hipSuccess;

@@ -19,21 +19,13 @@
 // column itself in the previous sweep), and a unit is taken only by a running
 // workgroup, so the waits always end however many workgroups are resident.
 // Each cell is updated by the same cell team as the single-problem kernels,
-// in the same serial Gauss-Seidel order of Alg. 1.
+// in the same serial Gauss-Seidel order of Alg. 1.  (The batched residuals
+// run one wavefront per cell: nrxx_wsweep.hip.)
 #include "nrxx_device.hpp"
 
 namespace nrxx {
 namespace {
 
-__device__ __forceinline__ int find_slot(const BLevel *__restrict__ tab, int nslot, int cell) {
-  int lo = 0, hi = nslot - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (tab[mid].cell0 <= cell) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
 
 // Copies a problem's level constants into LDS once per workgroup: the cell
 // team reads them many times, and reading them through the table in global
@@ -190,32 +182,6 @@ __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__
   }
 }
 
-// role 0: Rbar = rhs - R(st) (problems that continue to a coarser level);
-// role 1: rhs = R(fbar) + RH (eq. (22));
-// role 2: partial[cell0 + cell] = weighted |rhs - R(st)|^2 ds (eq. (28)).
-template <int M, int ORDER, int NW, int MODE>
-__global__ __launch_bounds__(NW * WAVE) void k_bresidual(const BLevel *__restrict__ tab, int nslot,
-                                                         const int *__restrict__ active, int role,
-                                                         double *partial) {
-  __shared__ double lds[Lay<M, NW>::TOTAL];
-  __shared__ LevelArgs sA;
-  const int slot = find_slot(tab, nslot, blockIdx.x);
-  const BLevel &B = tab[slot];
-  if (!active[B.inst] || (role == 0 && !B.cont)) return;
-  stage_args(B.A, sA);
-  const int cell = blockIdx.x - B.cell0;
-  const int i = cell % sA.nx, j = cell / sA.nx;
-  if (role == 1)
-    cell_team<double, M, ORDER, NW, MODE>(sA, lds, B.fbar, nullptr, B.RH, B.rhs, nullptr, i, j,
-                                          nullptr);
-  else if (role == 0)
-    cell_team<double, M, ORDER, NW, MODE>(sA, lds, B.st, B.rhs, nullptr, B.Rbar, nullptr, i, j,
-                                          nullptr);
-  else
-    cell_team<double, M, ORDER, NW, MODE>(sA, lds, B.st, B.rhs, nullptr, nullptr,
-                                          partial + B.cell0, i, j, nullptr);
-}
-
 // Restriction of level k (tabF) into level k+1 (tabC), one wavefront per
 // coarse cell of the group.
 template <int M>
@@ -323,7 +289,7 @@ __global__ void k_bfill(int *p, int n, int v) {
 // but more cells in flight per CU, which pays when many problems supply
 // independent columns.
 bool batch_width_ok(int M, int nw) {
-  if (M < MMIN || M > MMAX) return false;
+  if (M < MMIN || M > MTEAM) return false;
   return nw == 4 || nw == 2 || nw == 1 || (nw == 8 && M <= 5);
 }
 
@@ -431,30 +397,10 @@ int bsweep_resident(int M, int order, int nw, int split) {
 }
 int bsweep_resident32(int M, int order, int nw) { return resident_t<float, true>(M, order, nw); }
 
-hipError_t launch_bresidual(int M, int order, int ncell, const BLevel *tab, int nslot,
-                            const int *active, int role, double *partial, hipStream_t s) {
-  if (ncell <= 0) return hipSuccess;
-  NRXX_DISPATCH_M(M, {
-    constexpr int NW = TeamWidth<MM>::NW;
-    if (role == 1) {
-      if (order == 1)
-        hipLaunchKernelGGL((k_bresidual<MM, 1, NW, MODE_FAS>), dim3(ncell), dim3(NW * WAVE), 0, s, tab, nslot, active, role, partial);
-      else
-        hipLaunchKernelGGL((k_bresidual<MM, 2, NW, MODE_FAS>), dim3(ncell), dim3(NW * WAVE), 0, s, tab, nslot, active, role, partial);
-    } else {
-      if (order == 1)
-        hipLaunchKernelGGL((k_bresidual<MM, 1, NW, MODE_DEFECT>), dim3(ncell), dim3(NW * WAVE), 0, s, tab, nslot, active, role, partial);
-      else
-        hipLaunchKernelGGL((k_bresidual<MM, 2, NW, MODE_DEFECT>), dim3(ncell), dim3(NW * WAVE), 0, s, tab, nslot, active, role, partial);
-    }
-  });
-  return hipGetLastError();
-}
-
 hipError_t launch_brestrict(int M, int ncell_coarse, const BLevel *tabF, const BLevel *tabC,
                             int nslot, const int *active, int *err, hipStream_t s) {
   if (ncell_coarse <= 0) return hipSuccess;
-  NRXX_DISPATCH_M(M, {
+  NRXX_DISPATCH_MW(M, {
     hipLaunchKernelGGL((k_brestrict<MM>), dim3(ncell_coarse), dim3(WAVE), 0, s, tabF, tabC, nslot, active, err);
   });
   return hipGetLastError();
@@ -463,7 +409,7 @@ hipError_t launch_brestrict(int M, int ncell_coarse, const BLevel *tabF, const B
 hipError_t launch_bcopy(int M, int ncell, const BLevel *tab, int nslot, const int *active,
                         hipStream_t s) {
   if (ncell <= 0) return hipSuccess;
-  NRXX_DISPATCH_M(M, {
+  NRXX_DISPATCH_MW(M, {
     hipLaunchKernelGGL((k_bcopy<MM>), dim3(ncell), dim3(WAVE), 0, s, tab, nslot, active);
   });
   return hipGetLastError();
@@ -472,7 +418,7 @@ hipError_t launch_bcopy(int M, int ncell, const BLevel *tab, int nslot, const in
 hipError_t launch_bcorrect(int M, int ncell_coarse, const BLevel *tabF, const BLevel *tabC,
                            int nslot, const int *active, int *err, hipStream_t s) {
   if (ncell_coarse <= 0) return hipSuccess;
-  NRXX_DISPATCH_M(M, {
+  NRXX_DISPATCH_MW(M, {
     hipLaunchKernelGGL((k_bcorrect<MM>), dim3(ncell_coarse), dim3(WAVE), 0, s, tabF, tabC, nslot, active, err);
   });
   return hipGetLastError();
@@ -488,7 +434,7 @@ hipError_t launch_bsum(const BLevel *tab, int nslot, int stride, const int *acti
 hipError_t launch_bmass_scale(int M, int ncell, const BLevel *tab, int nslot, const int *active,
                               const double *mass, hipStream_t s) {
   if (ncell <= 0) return hipSuccess;
-  NRXX_DISPATCH_M(M, {
+  NRXX_DISPATCH_MW(M, {
     hipLaunchKernelGGL((k_bmass_scale<MM>), dim3(ncell), dim3(WAVE), 0, s, tab, nslot, active, mass);
   });
   return hipGetLastError();

@@ -36,6 +36,7 @@ struct nrxx_batch {
     std::vector<void *> owned;
     int nw = 0, grid = 0, major = 0, split = 1;
     int kernel = 0;  // 0: cell-team sweep kernel, 1: wavefront-per-cell sweep kernel
+    int rows = 1;    // wavefront-per-cell kernel: rows per wait/acquire/release
     double tuned_ms = 0.0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -94,6 +95,7 @@ int bhip(nrxx_batch *b, hipError_t e, const char *what) {
   } while (0)
 
 using Group = nrxx_batch::Group;
+
 
 double cycle_cells(const nrxx_batch *b, int inst) {
   const nrxx_problem &P = b->P[inst];
@@ -178,7 +180,7 @@ int smooth(nrxx_batch *b, Group &G, int k, int nsteps, int which) {
     }
     if (G.kernel == 1)
       BCHK(launch_wsweep(G.M, G.order, grid, G.dtab[k], G.units[G.major][which][k], U, nsw, dirs,
-                         G.cnt[k], G.cols[k], b->active, b->derr, b->dabort, b->wait_ticks,
+                         G.cnt[k], G.cols[k], b->active, b->derr, b->dabort, b->wait_ticks, G.rows,
                          G.stream));
     else
       BCHK(launch_bsweep(G.M, G.order, G.nw, G.split, grid, G.dtab[k], G.units[G.major][which][k], U,
@@ -225,11 +227,11 @@ int vcycle(nrxx_batch *b, Group &G, int k) {
   if (G.U[0][k] == 0) return NRXX_OK;
   rc = smooth(b, G, k, b->s1, 0);
   if (rc) return rc;
-  BCHK(launch_bresidual(G.M, G.order, G.ncell[k], G.dtab[k], nslot, b->active, 0, nullptr, G.stream));
+  BCHK(launch_wresidual(G.M, G.order, G.ncell[k], G.dtab[k], nslot, b->active, 0, nullptr, G.stream));
   BCHK(launch_brestrict(G.M, G.ncell[k + 1], G.dtab[k], G.dtab[k + 1], nslot, b->active, b->derr,
                         G.stream));
-  BCHK(launch_bresidual(G.M, G.order, G.ncell[k + 1], G.dtab[k + 1], nslot, b->active, 1, nullptr,
-                        G.stream));
+  BCHK(launch_wresidual(G.M, G.order, G.ncell[k + 1], G.dtab[k + 1], nslot, b->active, 1, nullptr,
+                         G.stream));
   BCHK(launch_bcopy(G.M, G.ncell[k + 1], G.dtab[k + 1], nslot, b->active, G.stream));
   for (int r = 0; r < b->gamma; ++r) {
     rc = vcycle(b, G, k + 1);
@@ -242,7 +244,7 @@ int vcycle(nrxx_batch *b, Group &G, int k) {
 
 int norms_enqueue(nrxx_batch *b, Group &G) {
   const int nslot = (int)G.inst.size();
-  BCHK(launch_bresidual(G.M, G.order, G.ncell[0], G.dtab[0], nslot, b->active, 2, G.partial, G.stream));
+  BCHK(launch_wresidual(G.M, G.order, G.ncell[0], G.dtab[0], nslot, b->active, 2, G.partial, G.stream));
   BCHK(launch_bsum(G.dtab[0], nslot, G.stride, b->active, G.partial, 0, b->norms, G.stream));
   return NRXX_OK;
 }
@@ -449,7 +451,13 @@ int nrxx_batch_create(const nrxx_problem *probs, int32_t n, void *hip_stream, nr
     if (ok) ok = hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking) == hipSuccess;
     if (ok) ok = hipEventCreateWithFlags(&G.done, hipEventDisableTiming) == hipSuccess;
     G.nw = batch_default_width(G.M);
-    G.grid = bsweep_resident(G.M, G.order, G.nw, 1);
+    if (G.M > MTEAM) {  // past the cell team's largest M: one wavefront per cell
+      G.kernel = 1;
+      G.rows = 1;
+      G.grid = wsweep_resident(G.M, G.order);
+    } else {
+      G.grid = bsweep_resident(G.M, G.order, G.nw, 1);
+    }
     if (G.grid < 1) ok = false;
     G.major = 0;
   }
@@ -523,6 +531,7 @@ int nrxx_batch_get_tuning(const nrxx_batch *b, int group, nrxx_batch_tuning *t) 
   t->split = G.split;
   t->block_ms = G.tuned_ms;
   t->kernel = G.kernel;
+  t->rows_per_sync = G.rows;
   return NRXX_OK;
 }
 
@@ -531,14 +540,19 @@ int nrxx_batch_set_tuning(nrxx_batch *b, int group, const nrxx_batch_tuning *t) 
   if (!t || group < 0 || group >= (int)b->g.size()) return bfail(b, NRXX_EINVAL, "bad group");
   Group &G = b->g[group];
   if (t->kernel != 0 && t->kernel != 1) return bfail(b, NRXX_EINVAL, "kernel %d", t->kernel);
+  if (t->kernel == 0 && G.M > MTEAM)
+    return bfail(b, NRXX_EINVAL, "M = %d > %d needs the wavefront-per-cell kernel", G.M, MTEAM);
+  if (t->kernel == 1 && (t->rows_per_sync < 1 || t->rows_per_sync > 65535))
+    return bfail(b, NRXX_EINVAL, "rows_per_sync %d", t->rows_per_sync);
   if (t->kernel == 0 && !batch_width_ok(G.M, t->team_width))
     return bfail(b, NRXX_EINVAL, "team width %d", t->team_width);
   if (t->grid < 1 || (t->unit_order != 0 && t->unit_order != 1) || (t->split != 0 && t->split != 1))
     return bfail(b, NRXX_EINVAL, "bad grid, unit order or split");
   if (G.kernel != t->kernel || G.nw != t->team_width || G.grid != t->grid ||
-      G.major != t->unit_order || G.split != t->split)
+      G.major != t->unit_order || G.split != t->split || (t->kernel == 1 && G.rows != t->rows_per_sync))
     drop_graph(G);
   G.kernel = t->kernel;
+  if (t->kernel == 1) G.rows = t->rows_per_sync;
   if (t->kernel == 0) G.nw = t->team_width;
   G.grid = t->grid;
   G.major = t->unit_order;
@@ -708,7 +722,7 @@ int nrxx_batch_autotune(nrxx_batch *b, double *const *states) {
     };
     // candidates: (kernel, team width, split, grid, unit order)
     struct Cand {
-      int kernel, nw, split, grid, major;
+      int kernel, nw, split, grid, major, rows;
     };
     std::vector<Cand> cands;
     const int widths[4] = {8, 4, 2, 1};
@@ -718,16 +732,16 @@ int nrxx_batch_autotune(nrxx_batch *b, double *const *states) {
         const int res = bsweep_resident(G.M, G.order, widths[wi], sp);
         if (res < 1) continue;
         for (int gr : {res, std::max(1, res / 2)})
-          for (int m = 0; m < 2; ++m) cands.push_back({0, widths[wi], sp, gr, m});
+          for (int m = 0; m < 2; ++m) cands.push_back({0, widths[wi], sp, gr, m, G.rows});
       }
     {
       const int res = wsweep_resident(G.M, G.order);
       if (res >= 1)
         for (int gr : {res, std::max(1, res / 2)})
-          for (int m = 0; m < 2; ++m) cands.push_back({1, G.nw, G.split, gr, m});
+          for (int m = 0; m < 2; ++m) cands.push_back({1, G.nw, G.split, gr, m, 1});
     }
     double best = 1e300;
-    Cand keep{G.kernel, G.nw, G.split, G.grid, G.major};
+    Cand keep{G.kernel, G.nw, G.split, G.grid, G.major, G.rows};
     for (const Cand &cd : cands) {
       if (!ok) break;
       G.kernel = cd.kernel;
@@ -735,6 +749,7 @@ int nrxx_batch_autotune(nrxx_batch *b, double *const *states) {
       G.split = cd.split;
       G.grid = cd.grid;
       G.major = cd.major;
+      G.rows = cd.rows;
       float ms = 0.f;
       for (int rep = 0; rep < 2 && ok; ++rep) {  // the first run loads the code object
         ok = restore();
@@ -764,6 +779,7 @@ int nrxx_batch_autotune(nrxx_batch *b, double *const *states) {
     G.split = keep.split;
     G.grid = keep.grid;
     G.major = keep.major;
+    G.rows = keep.rows;
     G.tuned_ms = best;
     drop_graph(G);
   }

@@ -418,7 +418,8 @@ __device__ __forceinline__ Real hermite(int n, Real x) {
 // half-range moments K_n (in LDS) and He_k He_l = sum_j k! l! / (j! (k-j)!
 // (l-j)!) He_{k+l-2j}.  The integer coefficient is carried as a running
 // product, c_j = c_{j-1} (k-j+1) (l-j+1) / j (every step divides exactly;
-// below 2^24 for the k <= M, l <= M + 1 used here), so the loop reads no
+// in 64 bits, as the products pass 2^31 at M = 10; the c_j stay below 2^24,
+// exact in FP32, for the M <= 8 of the FP32 kernels), so the loop reads no
 // table from global memory, whose cached lines the acquires of the sweep
 // kernels keep invalidating.  (Unrolling this loop spills registers in the
 // sweep kernels.)
@@ -427,7 +428,7 @@ __device__ __forceinline__ Real halfI(const Real *K, int k, int l) {
   if (l < 0) return Real(0.0);
   const int jm = k < l ? k : l;
   Real acc = K[k + l];
-  int cf = 1;
+  long long cf = 1;
   for (int j = 1; j <= jm; ++j) {
     cf = cf * (k - j + 1) * (l - j + 1) / j;
     acc += Real(cf) * K[k + l - 2 * j];
@@ -1044,6 +1045,17 @@ __device__ __forceinline__ bool wait_at_least(const int *flag, int target, int *
 // observed visible to the loads that follow.
 __device__ __forceinline__ void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
+// Table slot of a group's cell (entries sorted by their first cell).
+__device__ __forceinline__ int find_slot(const BLevel *__restrict__ tab, int nslot, int cell) {
+  int lo = 0, hi = nslot - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab[mid].cell0 <= cell) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Restriction (Sec. 3.2.2, eq. (24)-(25)): coarse cell (I, J) from fine cells
 // (2I, 2J), (2I+1, 2J), (2I, 2J+1), (2I+1, 2J+1).
 // One wavefront; lds holds RestrictLds<M>::N doubles; the coarse records
@@ -1164,7 +1176,9 @@ __device__ void correct_cell(const LevelArgs &Af, double *__restrict__ fine,
 }  // namespace
 }  // namespace nrxx
 
-// Host-side dispatch of a runtime expansion order to the template argument MM.
+// Host-side dispatch of a runtime expansion order to the template argument
+// MM: NRXX_DISPATCH_M for the kernels built up to MTEAM (cell teams, FP32
+// blocks), NRXX_DISPATCH_MW for those built up to MMAX.
 #define NRXX_DISPATCH_M(M, BODY)                  \
   switch (M) {                                    \
     case 3: { constexpr int MM = 3; BODY; } break; \
@@ -1174,4 +1188,16 @@ __device__ void correct_cell(const LevelArgs &Af, double *__restrict__ fine,
     case 7: { constexpr int MM = 7; BODY; } break; \
     case 8: { constexpr int MM = 8; BODY; } break; \
     default: return hipErrorInvalidValue;         \
+  }
+#define NRXX_DISPATCH_MW(M, BODY)                   \
+  switch (M) {                                      \
+    case 3: { constexpr int MM = 3; BODY; } break;   \
+    case 4: { constexpr int MM = 4; BODY; } break;   \
+    case 5: { constexpr int MM = 5; BODY; } break;   \
+    case 6: { constexpr int MM = 6; BODY; } break;   \
+    case 7: { constexpr int MM = 7; BODY; } break;   \
+    case 8: { constexpr int MM = 8; BODY; } break;   \
+    case 9: { constexpr int MM = 9; BODY; } break;   \
+    case 10: { constexpr int MM = 10; BODY; } break; \
+    default: return hipErrorInvalidValue;           \
   }

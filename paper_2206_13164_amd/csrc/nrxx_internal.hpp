@@ -8,7 +8,11 @@
 namespace nrxx {
 
 constexpr int MMIN = 3;
-constexpr int MMAX = 8;
+// Largest expansion order: the wavefront-per-cell kernels and the light
+// per-cell kernels take M up to MMAX; the cell-team kernels (whose LDS holds
+// eight dense coefficient cubes) and the FP32 blocks stop at MTEAM.
+constexpr int MMAX = 10;
+constexpr int MTEAM = 8;
 
 __host__ __device__ constexpr int nalpha(int M) { return (M + 1) * (M + 2) * (M + 3) / 6; }
 __host__ __device__ constexpr int record_stride(int M) { return (nalpha(M) + 3 + 7) / 8 * 8; }
@@ -128,15 +132,27 @@ int bsweep_resident(int M, int order, int nw, int split);
 // The wavefront-per-cell form of the same work-queue sweep (nrxx_wsweep.hip):
 // same units, order, counters and waits; every wavefront of a workgroup
 // takes its own units.  FP64 only.
+// kb: rows of a column taken per wait/acquire/release (>= 1).  st_ovr /
+// rhs_ovr (non-null: a one-problem table) replace the table's state and
+// right-hand side.
 hipError_t launch_wsweep(int M, int order, int grid, const BLevel *tab, const int *units, int U,
                          int nsweep, unsigned dirs, int *queue, int cstride, const int *active,
-                         int *err, int *abort_flag, unsigned long long limit, hipStream_t s);
+                         int *err, int *abort_flag, unsigned long long limit, int kb,
+                         hipStream_t s, double *st_ovr = nullptr, const double *rhs_ovr = nullptr);
+// One problem's residual with one wavefront per cell (modes of
+// launch_residual); used for M > MTEAM.
+hipError_t launch_wresidual1(int M, const LevelArgs &A, const double *st, const double *rhs,
+                             const double *Radd, double *out, double *norm_part, int mode,
+                             hipStream_t s);
 int wsweep_resident(int M, int order);  // workgroups resident at once (0 if unknown)
-int wsweep_wavefronts_per_group();
-int bsweep_resident32(int M, int order, int nw);
-// role 0: Rbar = rhs - R(st); 1: rhs = R(fbar) + RH; 2: partial = weighted squares
-hipError_t launch_bresidual(int M, int order, int ncell, const BLevel *tab, int nslot,
+// Batched residuals with one wavefront per cell.  role 0: Rbar = rhs - R(st)
+// (problems that continue to a coarser level); 1: rhs = R(fbar) + RH
+// (eq. (22)); 2: partial = weighted squares (eq. (28)).  Bit-identical to the
+// cell-team residual.
+hipError_t launch_wresidual(int M, int order, int ncell, const BLevel *tab, int nslot,
                             const int *active, int role, double *partial, hipStream_t s);
+int wsweep_wavefronts_per_group(int M);
+int bsweep_resident32(int M, int order, int nw);
 hipError_t launch_brestrict(int M, int ncell_coarse, const BLevel *tabF, const BLevel *tabC,
                             int nslot, const int *active, int *err, hipStream_t s);
 hipError_t launch_bcopy(int M, int ncell, const BLevel *tab, int nslot, const int *active,

@@ -367,18 +367,23 @@ __global__ __launch_bounds__(1024) void k_euler_dt(LevelArgs A, const double *__
 
 // The Euler update of every cell from the same old state: f <- normalise(f
 // + dt R(f)) (Sec. 2.4), given d = -R(f) in the cell's basis (the defect
-// with a zero right-hand side).  One wavefront per cell, four per workgroup;
-// a wavefront without a cell returns before any wavefront-level sync.
+// with a zero right-hand side).  One wavefront per cell, EW per workgroup
+// (four; one above MTEAM, where the dense cubes are large); a wavefront
+// without a cell returns before any wavefront-level sync.
 template <int M>
-__global__ __launch_bounds__(4 * WAVE) void k_euler_update(LevelArgs A, double *__restrict__ st,
-                                                           const double *__restrict__ d,
-                                                           const double *__restrict__ dt,
-                                                           int *err) {
+struct EulerW {
+  static constexpr int W = M <= MTEAM ? 4 : 1;
+};
+template <int M>
+__global__ __launch_bounds__(EulerW<M>::W * WAVE) void k_euler_update(
+    LevelArgs A, double *__restrict__ st, const double *__restrict__ d,
+    const double *__restrict__ dt, int *err) {
   using g = G<M>;
   constexpr int WSZ = 3 * g::CUBE + g::MISC;
-  __shared__ double lds[4 * WSZ];
+  constexpr int EW = EulerW<M>::W;
+  __shared__ double lds[EW * WSZ];
   const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-  const int cell = blockIdx.x * 4 + wv;
+  const int cell = blockIdx.x * EW + wv;
   if (cell >= A.nx * A.ny) return;
   Wave<double, M> W;
   W.init(lds + wv * WSZ, lane);
@@ -404,15 +409,17 @@ __global__ __launch_bounds__(4 * WAVE) void k_euler_update(LevelArgs A, double *
 
 hipError_t launch_euler_dt(int M, const LevelArgs &A, const double *st, double *dt_out,
                            hipStream_t s) {
-  NRXX_DISPATCH_M(M, hipLaunchKernelGGL((k_euler_dt<MM>), dim3(1), dim3(1024), 0, s, A, st, dt_out));
+  NRXX_DISPATCH_MW(M, hipLaunchKernelGGL((k_euler_dt<MM>), dim3(1), dim3(1024), 0, s, A, st, dt_out));
   return hipGetLastError();
 }
 
 hipError_t launch_euler_update(int M, const LevelArgs &A, double *st, const double *d,
                                const double *dt, int *err, hipStream_t s) {
-  const int blocks = (A.nx * A.ny + 3) / 4;
-  NRXX_DISPATCH_M(M, hipLaunchKernelGGL((k_euler_update<MM>), dim3(blocks), dim3(4 * WAVE), 0, s, A,
-                                        st, d, dt, err));
+  NRXX_DISPATCH_MW(M, {
+    constexpr int EW = EulerW<MM>::W;
+    const int blocks = (A.nx * A.ny + EW - 1) / EW;
+    hipLaunchKernelGGL((k_euler_update<MM>), dim3(blocks), dim3(EW * WAVE), 0, s, A, st, d, dt, err);
+  });
   return hipGetLastError();
 }
 
@@ -551,6 +558,7 @@ hipError_t launch_residual(int M, const LevelArgs &A, const double *st, const do
                            const double *Radd, double *out, double *norm_part, int mode,
                            hipStream_t s) {
   const int ncell = A.nx * A.ny;
+  if (M > MTEAM) return launch_wresidual1(M, A, st, rhs, Radd, out, norm_part, mode, s);
   NRXX_DISPATCH_M(M, {
     constexpr int NW = TeamWidth<MM>::NW;
     if (mode == 0) {
@@ -571,7 +579,7 @@ hipError_t launch_residual(int M, const LevelArgs &A, const double *st, const do
 hipError_t launch_restrict(int M, const LevelArgs &Af, const double *fine, const double *fineR,
                            double *coarse, double *coarseR, int *err, hipStream_t s) {
   const int nc = (Af.nx / 2) * (Af.ny / 2);
-  NRXX_DISPATCH_M(M, {
+  NRXX_DISPATCH_MW(M, {
     hipLaunchKernelGGL((k_restrict<MM>), dim3(nc), dim3(WAVE), 0, s, Af, fine, fineR, coarse, coarseR, err);
   });
   return hipGetLastError();
@@ -580,7 +588,7 @@ hipError_t launch_restrict(int M, const LevelArgs &Af, const double *fine, const
 hipError_t launch_correct(int M, const LevelArgs &Af, double *fine, const double *cnew,
                           const double *cold, int *err, hipStream_t s) {
   const int nc = (Af.nx / 2) * (Af.ny / 2);
-  NRXX_DISPATCH_M(M, {
+  NRXX_DISPATCH_MW(M, {
     hipLaunchKernelGGL((k_correct<MM>), dim3(nc), dim3(WAVE), 0, s, Af, fine, cnew, cold, err);
   });
   return hipGetLastError();
@@ -589,7 +597,7 @@ hipError_t launch_correct(int M, const LevelArgs &Af, double *fine, const double
 hipError_t launch_init_maxwellian(int M, const LevelArgs &A, double *st, double rho, double u1,
                                   double u2, double th, hipStream_t s) {
   const int ncell = A.nx * A.ny;
-  NRXX_DISPATCH_M(M, {
+  NRXX_DISPATCH_MW(M, {
     const size_t tot = (size_t)ncell * G<MM>::STRIDE;
     int blocks = (int)((tot + 255) / 256);
     if (blocks > 4096) blocks = 4096;
@@ -615,7 +623,7 @@ hipError_t launch_block_scale(const LevelArgs &A, const double *part, double tau
 hipError_t launch_mass_scale(int M, const LevelArgs &A, double *st, const double *mass,
                              double mass0, hipStream_t s) {
   const int ncell = A.nx * A.ny;
-  NRXX_DISPATCH_M(M, {
+  NRXX_DISPATCH_MW(M, {
     const size_t tot = (size_t)ncell * G<MM>::STRIDE;
     int blocks = (int)((tot + 255) / 256);
     if (blocks > 4096) blocks = 4096;
@@ -646,7 +654,7 @@ FieldIdx field_idx() {
 hipError_t launch_init_fields(int M, const LevelArgs &A, double *st, const float *fields, int fnx,
                               int fny, int *err, hipStream_t s) {
   const FieldIdx ix = field_idx();
-  NRXX_DISPATCH_M(M, {
+  NRXX_DISPATCH_MW(M, {
     const size_t tot = (size_t)A.nx * A.ny * G<MM>::STRIDE;
     int blocks = (int)((tot + 255) / 256);
     if (blocks > 4096) blocks = 4096;
@@ -659,7 +667,7 @@ hipError_t launch_state_fields(int M, const LevelArgs &A, const double *st, floa
                                hipStream_t s) {
   const FieldIdx ix = field_idx();
   const int ncell = A.nx * A.ny;
-  NRXX_DISPATCH_M(M, {
+  NRXX_DISPATCH_MW(M, {
     int blocks = (ncell + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL((k_state_fields<MM>), dim3(blocks), dim3(256), 0, s, ncell, st, ix, fields);

@@ -30,13 +30,41 @@
 namespace nrxx {
 namespace {
 
-// Tables of the packed layouts of order M.
+// A wavefront-uniform value moved to scalar registers: vector registers are
+// what limits the number of cells in flight, and a uniform double held in a
+// vector register takes two of them.
+__device__ __forceinline__ double uni(double x) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  return __builtin_bit_cast(double, (unsigned long long)hi << 32 | lo);
+}
+
+// Packed layouts of order M.  Every line along the fastest index is
+// preceded by a run of zeros as long as the basis change reaches back (M in
+// L1 and L2, M / 2 in L3), so a basis-change pass reads alpha - k e_d for
+// every k with no select: below the line's start it reads a zero.
+template <int M>
+constexpr int pad_size(int lay) {
+  int s = 0;
+  if (lay == 3) {
+    for (int a1 = 0; a1 <= M; ++a1)
+      for (int a2 = 0; a1 + a2 <= M; ++a2) s += M / 2 + (M - a1 - a2) / 2 + 1;
+  } else {
+    for (int m = 0; 2 * m <= M; ++m)
+      for (int b = 0; b + 2 * m <= M; ++b) s += M + (M - 2 * m - b + 1);
+  }
+  return s;
+}
+
 template <int M>
 struct Pack {
   static constexpr int NE = neven(M);
   static constexpr int D1 = M + 1, D2 = (M + 1) * (M + 1);
   static constexpr int CUBE = D2 * (M / 2 + 1);
   static constexpr int N = nalpha(M);
+  static constexpr int P12 = pad_size<M>(1), P3 = pad_size<M>(3);
+  static constexpr int PV = P12 > P3 ? P12 : P3;  // one padded vector
   // per slot e (the even-alpha_3 coefficients in graded order, as in the
   // cell team): alpha, position in the graded record order, cube address,
   // positions in L1, L2, L3
@@ -52,16 +80,22 @@ constexpr Pack<M> make_pack() {
   int16_t l1[P::CUBE] = {}, l2[P::CUBE] = {}, l3[P::CUBE] = {};
   int k = 0;
   for (int m = 0; 2 * m <= M; ++m)
-    for (int a2 = 0; a2 + 2 * m <= M; ++a2)
+    for (int a2 = 0; a2 + 2 * m <= M; ++a2) {
+      k += M;  // zeros ahead of the line
       for (int a1 = 0; a1 + a2 + 2 * m <= M; ++a1) l1[a1 + P::D1 * a2 + P::D2 * m] = (int16_t)k++;
+    }
   k = 0;
   for (int m = 0; 2 * m <= M; ++m)
-    for (int a1 = 0; a1 + 2 * m <= M; ++a1)
+    for (int a1 = 0; a1 + 2 * m <= M; ++a1) {
+      k += M;
       for (int a2 = 0; a1 + a2 + 2 * m <= M; ++a2) l2[a1 + P::D1 * a2 + P::D2 * m] = (int16_t)k++;
+    }
   k = 0;
   for (int a1 = 0; a1 <= M; ++a1)
-    for (int a2 = 0; a1 + a2 <= M; ++a2)
+    for (int a2 = 0; a1 + a2 <= M; ++a2) {
+      k += M / 2;
       for (int m = 0; a1 + a2 + 2 * m <= M; ++m) l3[a1 + P::D1 * a2 + P::D2 * m] = (int16_t)k++;
+    }
   for (int c = 0; c < P::CUBE; ++c) {
     t.map1[c] = l1[c];
     t.map2[c] = l2[c];
@@ -96,6 +130,8 @@ __constant__ Pack<5> c_pack5 = make_pack<5>();
 __constant__ Pack<6> c_pack6 = make_pack<6>();
 __constant__ Pack<7> c_pack7 = make_pack<7>();
 __constant__ Pack<8> c_pack8 = make_pack<8>();
+__constant__ Pack<9> c_pack9 = make_pack<9>();
+__constant__ Pack<10> c_pack10 = make_pack<10>();
 
 template <int M>
 __device__ __forceinline__ const Pack<M> &pack_of() {
@@ -104,7 +140,9 @@ __device__ __forceinline__ const Pack<M> &pack_of() {
   else if constexpr (M == 5) return c_pack5;
   else if constexpr (M == 6) return c_pack6;
   else if constexpr (M == 7) return c_pack7;
-  else return c_pack8;
+  else if constexpr (M == 8) return c_pack8;
+  else if constexpr (M == 9) return c_pack9;
+  else return c_pack10;
 }
 
 // L1 position of alpha = (a1, a2, 2m), for coefficients used by name.
@@ -114,6 +152,7 @@ constexpr int l1pos(int a1, int a2, int m) {
 }
 template <int M>
 struct Named {
+  static constexpr int R0 = l1pos<M>(0, 0, 0);
   static constexpr int E1 = l1pos<M>(1, 0, 0), E2 = l1pos<M>(0, 1, 0);
   static constexpr int XX = l1pos<M>(2, 0, 0), YY = l1pos<M>(0, 2, 0), ZZ = l1pos<M>(0, 0, 1);
   static constexpr int X3 = l1pos<M>(3, 0, 0), X1Y2 = l1pos<M>(1, 2, 0), X1Z2 = l1pos<M>(1, 0, 1);
@@ -130,27 +169,54 @@ struct WTabs {
 template <int M>
 __device__ __forceinline__ void load_tabs(WTabs<M> &t) {
   const Pack<M> &P = pack_of<M>();
+#pragma unroll 1
   for (int x = threadIdx.x; x < Pack<M>::CUBE; x += blockDim.x) {
     t.map1[x] = P.map1[x];
     t.map2[x] = P.map2[x];
   }
+#pragma unroll 1
   for (int x = threadIdx.x; x < Pack<M>::N; x += blockDim.x) t.canon1[x] = P.canon1[x];
 }
 
-// Per-wavefront LDS (in Reals): the cell (L1), two work vectors A and B
-// (face states in L1 / L2, then basis-change temporaries in L2 / L3), the
-// basis-change input X (L1) and the wall tables.
+// Per-wavefront LDS (in Reals): the cell (L1); the own and neighbour face
+// states of a face (L1 for x faces, L2 for y faces); the basis-change input X
+// (L1) and its temporaries Y (L2) and Z (L3), whose zero runs must stay zero;
+// the wall tables; and (M <= 6) the records of the cell's stencil.
 template <int M>
 struct WLay {
   static constexpr int NE = neven(M);
-  static constexpr int V = NE;                       // one packed vector
-  static constexpr int C = 0, A = V, B = 2 * V, X = 3 * V;
-  static constexpr int KOFF = 4 * V;                 // K_n(a), n <= 2M+1
+  static constexpr int V = Pack<M>::PV;              // one padded vector
+  static constexpr int C = 0, FO = V, FN = 2 * V, X = 3 * V, Y = 4 * V, Z = 5 * V;
+  static constexpr int KOFF = 6 * V;                 // K_n(a), n <= 2M+1
   static constexpr int JOFF = KOFF + 2 * M + 2;      // J+_{kl}(a), (M+1)^2
   static constexpr int BC = JOFF + (M + 1) * (M + 1);  // broadcast slot
   static constexpr int OP = BC + 2;                  // own face-state parameters, 4 x 3
-  static constexpr int TOTAL = OP + 12;
+  // the records of the cell's stencil and its right-hand side, gathered
+  // from memory in one batch: [u1, u2, th, f_e (slot order)] each; at
+  // M >= 7 the LDS is better spent on cells in flight and records are read
+  // from memory where used
+  static constexpr bool GATHER = M <= 6;
+  static constexpr int GREC = (NE + 3 + 1) / 2 * 2;
+  static constexpr int GOFF = OP + 12;
+  static constexpr int TOTAL = GOFF + (GATHER ? 10 * GREC : 0);
 };
+
+// Zero the basis-change buffers once per kernel (their zero runs are never
+// written afterwards).
+template <typename Real, int M>
+__device__ __forceinline__ void wzero(Real *lw, int lane) {
+  using L = WLay<M>;
+  for (int x = L::X + lane; x < L::X + 3 * L::V; x += WAVE) lw[x] = Real(0.0);
+  wsync();
+}
+
+// Stencil records of a cell in the gather area: the cell, its x and y
+// neighbours at distance 1 and 2, and the right-hand side record.
+enum { Q_C = 0, Q_XP1, Q_XM1, Q_XP2, Q_XM2, Q_YP1, Q_YM1, Q_YP2, Q_YM2, Q_RHS, NQ };
+__device__ __forceinline__ int q_of(int D, int off) {
+  const int base = D == 0 ? Q_XP1 : Q_YP1;
+  return base + (off > 0 ? 0 : 1) + (off == 2 || off == -2 ? 2 : 0);
+}
 
 // The lane's slots: which coefficients it holds and where they live.
 template <int M>
@@ -181,11 +247,89 @@ struct WSlot {
 template <typename Real, int M>
 __device__ __forceinline__ void wload_cell(const Real *__restrict__ rec, const WSlot<M> &S,
                                            Cell<Real, M> &c) {
-  c.u1 = rec[0];
-  c.u2 = rec[1];
-  c.th = rec[2];
+  c.u1 = uni(rec[0]);
+  c.u2 = uni(rec[1]);
+  c.th = uni(rec[2]);
 #pragma unroll
   for (int r = 0; r < G<M>::SL; ++r) c.f[r] = S.ok[r] ? rec[3 + S.ci[r]] : Real(0.0);
+}
+
+// Loads every record the update of cell (i, j) reads -- the cell, its
+// neighbours at distance 1 (and 2 at second order) inside the grid, and the
+// right-hand side `rr` (if any) -- with all loads in flight at once, and
+// stores them in the gather area (lane e holds slot e).
+template <typename Real, int M, int ORDER, int Q0, int Q1>
+__device__ __forceinline__ void wgather_part(const LevelArgs &A, const Real *__restrict__ st,
+                                             const Real *__restrict__ rr, int i, int j, Real *G0,
+                                             const WSlot<M> &S, int lane) {
+  using g = G<M>;
+  using L = WLay<M>;
+  constexpr int NP = Q1 - Q0;
+  Real v[NP][g::SL], pv[NP];
+  bool have[NP];
+#pragma unroll
+  for (int t = 0; t < NP; ++t) {
+    const int q = Q0 + t;
+    int ii = i, jj = j;
+    if (q >= Q_XP1 && q <= Q_XM2) ii += (q == Q_XP1 ? 1 : q == Q_XM1 ? -1 : q == Q_XP2 ? 2 : -2);
+    if (q >= Q_YP1 && q <= Q_YM2) jj += (q == Q_YP1 ? 1 : q == Q_YM1 ? -1 : q == Q_YP2 ? 2 : -2);
+    const bool far = q == Q_XP2 || q == Q_XM2 || q == Q_YP2 || q == Q_YM2;
+    have[t] = ii >= 0 && ii < A.nx && jj >= 0 && jj < A.ny && !(far && ORDER == 1) &&
+              (q != Q_RHS || rr != nullptr);
+    if (have[t]) {
+      const Real *rec = recp<Real, M>(A, q == Q_RHS ? rr : st, ii, jj);
+#pragma unroll
+      for (int r = 0; r < g::SL; ++r) v[t][r] = S.ok[r] ? rec[3 + S.ci[r]] : Real(0.0);
+      pv[t] = rec[lane < 3 ? lane : 0];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NP; ++t) {
+    if (!have[t]) continue;
+    Real *Gq = G0 + (Q0 + t) * L::GREC;
+#pragma unroll
+    for (int r = 0; r < g::SL; ++r)
+      if (S.ok[r]) Gq[3 + lane + WAVE * r] = v[t][r];
+    if (lane < 3) Gq[lane] = pv[t];
+  }
+}
+
+// Loads every record the update of cell (i, j) reads -- the cell, its
+// neighbours at distance 1 (and 2 at second order) inside the grid, and the
+// right-hand side `rr` (if any) -- in two batches of loads in flight at
+// once, into the gather area (lane e holds slot e).
+template <typename Real, int M, int ORDER>
+__device__ __forceinline__ void wgather(const LevelArgs &A, const Real *__restrict__ st,
+                                        const Real *__restrict__ rr, int i, int j, Real *lw,
+                                        const WSlot<M> &S, int lane) {
+  if constexpr (WLay<M>::GATHER) {
+    Real *G0 = lw + WLay<M>::GOFF;
+    wgather_part<Real, M, ORDER, 0, 5>(A, st, rr, i, j, G0, S, lane);
+    wgather_part<Real, M, ORDER, 5, NQ>(A, st, rr, i, j, G0, S, lane);
+    wsync();
+  }
+}
+
+// Record q of the cell's stencil as a Cell: from the gather area, or (no
+// gather) from memory.
+template <typename Real, int M>
+__device__ __forceinline__ void cell_q(const LevelArgs &A, const Real *__restrict__ st,
+                                       const Real *__restrict__ rr, int i, int j, const Real *lw,
+                                       int q, const WSlot<M> &S, int lane, Cell<Real, M> &c) {
+  using L = WLay<M>;
+  if constexpr (L::GATHER) {
+    const Real *Gq = lw + L::GOFF + q * L::GREC;
+    c.u1 = uni(Gq[0]);
+    c.u2 = uni(Gq[1]);
+    c.th = uni(Gq[2]);
+#pragma unroll
+    for (int r = 0; r < G<M>::SL; ++r) c.f[r] = S.ok[r] ? Gq[3 + lane + WAVE * r] : Real(0.0);
+  } else {
+    int ii = i, jj = j;
+    if (q >= Q_XP1 && q <= Q_XM2) ii += (q == Q_XP1 ? 1 : q == Q_XM1 ? -1 : q == Q_XP2 ? 2 : -2);
+    if (q >= Q_YP1 && q <= Q_YM2) jj += (q == Q_YP1 ? 1 : q == Q_YM1 ? -1 : q == Q_YP2 ? 2 : -2);
+    wload_cell<Real, M>(recp<Real, M>(A, q == Q_RHS ? rr : st, ii, jj), S, c);
+  }
 }
 
 // v -> packed vector `buf` in layout L1 (lay = 1) or L2 (lay = 2)
@@ -198,7 +342,9 @@ __device__ __forceinline__ void wput(Real *buf, int lay, const WSlot<M> &S,
 }
 
 // Basis change by (du1, du2, dth) of the vector X (layout L1) through Y (L2)
-// and Z (L3); the result stays in registers.  Same arithmetic as bchange.
+// and Z (L3); the result stays in registers.  The terms are those of
+// bchange, added in the same order; a term beyond alpha_d reads a zero of the
+// layout's zero run instead of being selected away.
 template <typename Real, int M>
 __device__ __forceinline__ void wbchange(const Real *X, Real *Y, Real *Z, Real du1, Real du2,
                                          Real dth, const WSlot<M> &S, Real (&res)[G<M>::SL]) {
@@ -206,37 +352,46 @@ __device__ __forceinline__ void wbchange(const Real *X, Real *Y, Real *Z, Real d
   Real c[M + 1];
   tcoef<Real, M>(du1, dth, c);
 #pragma unroll
+  for (int k = 0; k <= M; ++k) c[k] = uni(c[k]);
+#pragma unroll
   for (int r = 0; r < g::SL; ++r) {
+    const Real *p = X + S.p1[r];
     Real x[M + 1];
 #pragma unroll
-    for (int k = 0; k <= M; ++k) x[k] = X[k <= S.a1[r] ? S.p1[r] - k : S.p1[r]];
+    for (int k = 0; k <= M; ++k) x[k] = p[-k];
     Real acc = x[0];
 #pragma unroll
-    for (int k = 1; k <= M; ++k) acc = fma(k <= S.a1[r] ? c[k] : Real(0.0), x[k], acc);
+    for (int k = 1; k <= M; ++k) acc = fma(c[k], x[k], acc);
     if (S.ok[r]) Y[S.p2[r]] = acc;
   }
   wsync();
   tcoef<Real, M>(du2, dth, c);
 #pragma unroll
+  for (int k = 0; k <= M; ++k) c[k] = uni(c[k]);
+#pragma unroll
   for (int r = 0; r < g::SL; ++r) {
+    const Real *p = Y + S.p2[r];
     Real x[M + 1];
 #pragma unroll
-    for (int k = 0; k <= M; ++k) x[k] = Y[k <= S.a2[r] ? S.p2[r] - k : S.p2[r]];
+    for (int k = 0; k <= M; ++k) x[k] = p[-k];
     Real acc = x[0];
 #pragma unroll
-    for (int k = 1; k <= M; ++k) acc = fma(k <= S.a2[r] ? c[k] : Real(0.0), x[k], acc);
+    for (int k = 1; k <= M; ++k) acc = fma(c[k], x[k], acc);
     if (S.ok[r]) Z[S.p3[r]] = acc;
   }
   wsync();
   tcoef<Real, M>(Real(0.0), dth, c);
 #pragma unroll
+  for (int k = 0; k <= M; k += 2) c[k] = uni(c[k]);
+#pragma unroll
   for (int r = 0; r < g::SL; ++r) {
+    const Real *p = Z + S.p3[r];
     Real x[M / 2 + 1];
 #pragma unroll
-    for (int k = 0; 2 * k <= M; ++k) x[k] = Z[k <= S.m[r] ? S.p3[r] - k : S.p3[r]];
+    for (int k = 0; 2 * k <= M; ++k) x[k] = p[-k];
     Real acc = x[0];
 #pragma unroll
-    for (int k = 1; 2 * k <= M; ++k) acc = fma(k <= S.m[r] ? c[2 * k] : Real(0.0), x[k], acc);
+    for (int k = 1; 2 * k <= M; ++k) acc = fma(c[2 * k], x[k], acc);
     res[r] = S.ok[r] ? acc : Real(0.0);
   }
   wsync();
@@ -369,7 +524,7 @@ __device__ void wwall_flux(const LevelArgs &A, int wall, Real u1, Real u2, Real 
   wsync();
   const Real uw1 = d == 1 ? Real(A.wall_u[wall]) : Real(0.0), uw2 = d == 0 ? Real(A.wall_u[wall]) : Real(0.0);
   Real t[g::SL];
-  wbchange<Real, M>(X, lw + L::A, lw + L::B, u1 - uw1, u2 - uw2, th - thw, S, t);
+  wbchange<Real, M>(X, lw + L::Y, lw + L::Z, u1 - uw1, u2 - uw2, th - thw, S, t);
 #pragma unroll
   for (int r = 0; r < g::SL; ++r) phi[r] += t[r];
 }
@@ -385,7 +540,7 @@ __device__ bool wnormalise(Real ou1, Real ou2, Real oth, const Real (&fs)[G<M>::
   Real *X = lw + L::X;
   wput<Real, M>(X, 1, S, fs);
   wsync();
-  const Real rho = X[0];
+  const Real rho = X[NM::R0];
   const Real fe1 = X[NM::E1], fe2 = X[NM::E2];
   const Real tr = X[NM::XX] + X[NM::YY] + X[NM::ZZ];
   const Real irho = Real(1.0) / rho;
@@ -395,7 +550,7 @@ __device__ bool wnormalise(Real ou1, Real ou2, Real oth, const Real (&fs)[G<M>::
              isfinite(u2n);
   if (!okp) return false;  // uniform branch
   Real t[g::SL];
-  wbchange<Real, M>(X, lw + L::A, lw + L::B, u1n - ou1, u2n - ou2, thn - oth, S, t);
+  wbchange<Real, M>(X, lw + L::Y, lw + L::Z, u1n - ou1, u2n - ou2, thn - oth, S, t);
   wput<Real, M>(X, 1, S, t);
   wsync();
   const Real zz = -(X[NM::XX] + X[NM::YY]);
@@ -442,24 +597,32 @@ __device__ __forceinline__ void wstore_record(Real *__restrict__ rec, Real u1, R
   }
 }
 
-// One Gauss-Seidel update of cell (i, j) by one wavefront (MODE_SWEEP of
-// cell_team): f <- normalise(f + dt (R_ij(f) - r)), R assembled in the cell
-// team's order.  A non-physical update sets bit 0 of *err and leaves the
-// cell unchanged.
-template <typename Real, int M, int ORDER>
+// Cell (i, j) by one wavefront, in the modes of cell_team:
+//  MODE_SWEEP : one Gauss-Seidel update, f <- normalise(f + dt (R_ij(f) - r))
+//               (Alg. 1); a non-physical update sets bit 0 of *err and leaves
+//               the cell unchanged;
+//  MODE_DEFECT: out = r - R(f) in the cell basis, norm_part[cell] = weighted
+//               norm^2 * ds (eq. (28));
+//  MODE_FAS   : out = R(f) + Radd (coarse right-hand side of eq. (22)).
+// R is assembled in the cell team's order with the same arithmetic.
+template <typename Real, int M, int ORDER, int MODE = MODE_SWEEP>
 __device__ void wave_cell(const LevelArgs &A, Real *lw, const WTabs<M> &T, const WSlot<M> &S,
                           int lane, Real *__restrict__ st, const Real *__restrict__ rhs, int i,
-                          int j, int *err) {
+                          int j, int *err, const Real *__restrict__ Radd = nullptr,
+                          Real *__restrict__ out = nullptr, Real *__restrict__ norm_part = nullptr) {
   using g = G<M>;
   using L = WLay<M>;
   using NM = Named<M>;
-  Real *bC = lw + L::C, *bA = lw + L::A, *bB = lw + L::B, *bX = lw + L::X;
+  Real *bC = lw + L::C, *bA = lw + L::FO, *bB = lw + L::FN, *bX = lw + L::X;
+  Real *bY = lw + L::Y, *bZ = lw + L::Z;
   const int nx = A.nx, ny = A.ny;
+  const Real *rr = MODE == MODE_FAS ? Radd : rhs;
+  wgather<Real, M, ORDER>(A, st, rr, i, j, lw, S, lane);
   Cell<Real, M> c;
-  wload_cell<Real, M>(recp<Real, M>(A, st, i, j), S, c);
+  cell_q<Real, M>(A, st, rr, i, j, lw, Q_C, S, lane, c);
   wput<Real, M>(bC, 1, S, c.f);
-  const Real rho = __shfl(c.f[0], 0);
-  const Real nu = Real(A.beta) * sqrt(Real(M_PI) / Real(2.0)) * rho * pow(c.th, Real(1.0) - Real(A.omega)) / Real(A.Kn);
+  const Real rho = uni(c.f[0]);  // f_0 sits in lane 0, slot 0
+  const Real nu = uni(Real(A.beta) * sqrt(Real(M_PI) / Real(2.0)) * rho * pow(c.th, Real(1.0) - Real(A.omega)) / Real(A.Kn));
   wsync();
   Real R[g::SL];
 #pragma unroll
@@ -477,17 +640,18 @@ __device__ void wave_cell(const LevelArgs &A, Real *lw, const WTabs<M> &T, const
     const int sd = (f & 1) ? -1 : 1;
     const Real side = (Real)sd;
     const bool flat = ORDER == 1 || k == 0 || k == n - 1;
-    auto rec_at = [&](int off) {
-      return D == 0 ? recp<Real, M>(A, st, i + off, j) : recp<Real, M>(A, st, i, j + off);
-    };
+
     // own face state
     Cell<Real, M> Xo;
     if (flat) Xo = c;
     else {
       Cell<Real, M> hi, lo;
-      wload_cell<Real, M>(rec_at(1), S, hi);
-      wload_cell<Real, M>(rec_at(-1), S, lo);
+      cell_q<Real, M>(A, st, rr, i, j, lw, q_of(D, 1), S, lane, hi);
+      cell_q<Real, M>(A, st, rr, i, j, lw, q_of(D, -1), S, lane, lo);
       face_state<Real, M>(c, hi, lo, A.limiter, false, side, Xo);
+      Xo.u1 = uni(Xo.u1);
+      Xo.u2 = uni(Xo.u2);
+      Xo.th = uni(Xo.th);
     }
     if (lane == 0) {
       op[3 * f] = Xo.u1;
@@ -513,13 +677,16 @@ __device__ void wave_cell(const LevelArgs &A, Real *lw, const WTabs<M> &T, const
       Cell<Real, M> Xn;
       {
         Cell<Real, M> nb;
-        wload_cell<Real, M>(rec_at(sd), S, nb);
+        cell_q<Real, M>(A, st, rr, i, j, lw, q_of(D, sd), S, lane, nb);
         if (nflat) Xn = nb;
         else {
           Cell<Real, M> far;
-          wload_cell<Real, M>(rec_at(2 * sd), S, far);
+          cell_q<Real, M>(A, st, rr, i, j, lw, q_of(D, 2 * sd), S, lane, far);
           if (sd > 0) face_state<Real, M>(nb, far, c, A.limiter, false, -side, Xn);
           else face_state<Real, M>(nb, c, far, A.limiter, false, -side, Xn);
+          Xn.u1 = uni(Xn.u1);
+          Xn.u2 = uni(Xn.u2);
+          Xn.th = uni(Xn.th);
         }
       }
       wput<Real, M>(bA, lay, S, Xo.f);
@@ -529,12 +696,12 @@ __device__ void wave_cell(const LevelArgs &A, Real *lw, const WTabs<M> &T, const
       const Real uL = sd > 0 ? (D == 0 ? Xo.u1 : Xo.u2) : (D == 0 ? Xn.u1 : Xn.u2);
       const Real uR = sd > 0 ? (D == 0 ? Xn.u1 : Xn.u2) : (D == 0 ? Xo.u1 : Xo.u2);
       const Real thL = sd > 0 ? Xo.th : Xn.th, thR = sd > 0 ? Xn.th : Xo.th;
-      const Real cL = Real(A.C) * sqrt(thL), cR = Real(A.C) * sqrt(thR);
-      const Real lamL = fmin(uL - cL, uR - cR);
-      const Real lamR = fmax(uL + cL, uR + cR);
+      const Real cL = uni(Real(A.C) * sqrt(thL)), cR = uni(Real(A.C) * sqrt(thR));
+      const Real lamL = uni(fmin(uL - cL, uR - cR));
+      const Real lamR = uni(fmax(uL + cL, uR + cR));
       int kase;
       Real wm, wp;
-      const Real iden = Real(1.0) / (lamR - lamL);
+      const Real iden = uni(Real(1.0) / (lamR - lamL));
       if (lamL >= Real(0.0)) { kase = 0; wm = Real(0.0); wp = Real(1.0); }
       else if (lamR <= Real(0.0)) { kase = 1; wm = Real(1.0); wp = Real(0.0); }
       else { kase = 2; wm = -lamL * iden; wp = lamR * iden; }
@@ -570,7 +737,7 @@ __device__ void wave_cell(const LevelArgs &A, Real *lw, const WTabs<M> &T, const
           ah[s][r] = a;
         }
       }
-      wsync();  // A and B are free: basis-change temporaries from here
+      wsync();
       Real Th[2][g::SL];
 #pragma unroll 1
       for (int s = 0; s < 2; ++s) {
@@ -589,7 +756,7 @@ __device__ void wave_cell(const LevelArgs &A, Real *lw, const WTabs<M> &T, const
           for (int r = 0; r < g::SL; ++r) a[r] = s == 0 ? ah[0][r] : ah[1][r];
           wput<Real, M>(bX, 1, S, a);
           wsync();
-          wbchange<Real, M>(bX, bA, bB, c.u1 - xu1, c.u2 - xu2, c.th - xth, S, t);
+          wbchange<Real, M>(bX, bY, bZ, c.u1 - xu1, c.u2 - xu2, c.th - xth, S, t);
         }
 #pragma unroll
         for (int r = 0; r < g::SL; ++r) {
@@ -640,7 +807,7 @@ __device__ void wave_cell(const LevelArgs &A, Real *lw, const WTabs<M> &T, const
 #pragma unroll
     for (int r = 0; r < g::SL; ++r) {
       const int p = S.p1[r];
-      Real fE = p == 0 ? rho : Real(0.0);
+      Real fE = p == NM::R0 ? rho : Real(0.0);
       if (p == NM::X3 || p == NM::X1Y2 || p == NM::X1Z2) fE += c1;
       if (p == NM::Y3 || p == NM::X2Y1 || p == NM::Y1Z2) fE += c2;
       if (A.collision == 2) fE = esbgk_coef<Real>(S.a1[r], S.a2[r], S.m[r], rho, b11, b12, b22, b33);
@@ -649,29 +816,57 @@ __device__ void wave_cell(const LevelArgs &A, Real *lw, const WTabs<M> &T, const
     }
   }
   Real rv[g::SL];
-  if (rhs) {
-    // right-hand side in the cell basis
-    Cell<Real, M> rr;
-    wload_cell<Real, M>(recp<Real, M>(A, rhs, i, j), S, rr);
-    if (rr.u1 == c.u1 && rr.u2 == c.u2 && rr.th == c.th) {
+  if (rr) {
+    // right-hand side (Alg. 1) or the restricted residual (eq. (22)) in the
+    // cell basis
+    Cell<Real, M> r0;
+    cell_q<Real, M>(A, st, rr, i, j, lw, Q_RHS, S, lane, r0);
+    if ((r0.u1 == c.u1 && r0.u2 == c.u2 && r0.th == c.th) || MODE == MODE_FAS) {
 #pragma unroll
-      for (int r = 0; r < g::SL; ++r) rv[r] = rr.f[r];
+      for (int r = 0; r < g::SL; ++r) rv[r] = r0.f[r];
     } else {
-      wput<Real, M>(bX, 1, S, rr.f);
+      wput<Real, M>(bX, 1, S, r0.f);
       wsync();
-      wbchange<Real, M>(bX, bA, bB, c.u1 - rr.u1, c.u2 - rr.u2, c.th - rr.th, S, rv);
+      wbchange<Real, M>(bX, bY, bZ, c.u1 - r0.u1, c.u2 - r0.u2, c.th - r0.th, S, rv);
     }
   }
-  const Real dt = local_dt<Real>(A, c.u1, c.u2, c.th, nu);
-  Real fs[g::SL];
+  if constexpr (MODE == MODE_SWEEP) {
+    const Real dt = uni(local_dt<Real>(A, c.u1, c.u2, c.th, nu));
+    Real fs[g::SL];
 #pragma unroll
-  for (int r = 0; r < g::SL; ++r) fs[r] = c.f[r] + dt * (rhs ? R[r] - rv[r] : R[r]);
-  Cell<Real, M> nc;
-  if (wnormalise<Real, M>(c.u1, c.u2, c.th, fs, lw, S, lane, nc))
-    wstore_record<Real, M>(const_cast<Real *>(recp<Real, M>(A, st, i, j)), nc.u1, nc.u2, nc.th,
-                           lw + L::X, T, lane);
-  else if (lane == 0)
-    atomicOr(err, 1);
+    for (int r = 0; r < g::SL; ++r) fs[r] = c.f[r] + dt * (rr ? R[r] - rv[r] : R[r]);
+    Cell<Real, M> nc;
+    if (wnormalise<Real, M>(c.u1, c.u2, c.th, fs, lw, S, lane, nc))
+      wstore_record<Real, M>(const_cast<Real *>(recp<Real, M>(A, st, i, j)), nc.u1, nc.u2, nc.th,
+                             lw + L::X, T, lane);
+    else if (lane == 0)
+      atomicOr(err, 1);
+  } else {
+    Real o[g::SL];
+#pragma unroll
+    for (int r = 0; r < g::SL; ++r)
+      o[r] = MODE == MODE_FAS ? R[r] + rv[r] : (rr ? rv[r] : Real(0.0)) - R[r];
+    const int cellidx = j * nx + i;
+    if (out) {
+      wput<Real, M>(bX, 1, S, o);
+      wsync();
+      wstore_record<Real, M>(out + (size_t)cellidx * g::STRIDE, c.u1, c.u2, c.th, bX, T, lane);
+    }
+    if (MODE == MODE_DEFECT && norm_part) {
+      // per-cell weight alpha! th^-|alpha| of eq. (28), reduced in the cell
+      // team's order
+      Real s2 = Real(0.0);
+#pragma unroll
+      for (int q = 0; q < g::SL; ++q) {
+        if (!S.ok[q]) continue;
+        const Real w = Real(c_fact.v[S.a1[q]]) * Real(c_fact.v[S.a2[q]]) * Real(c_fact.v[2 * S.m[q]]);
+        s2 += w * pow(c.th, -(Real)S.n[q]) * o[q] * o[q];
+      }
+#pragma unroll
+      for (int off = WAVE / 2; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
+      if (lane == 0) norm_part[cellidx] = s2 * Real(A.ds);
+    }
+  }
 }
 
 }  // namespace

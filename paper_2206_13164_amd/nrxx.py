@@ -41,7 +41,7 @@ class Problem(ctypes.Structure):
 class BatchTuning(ctypes.Structure):
     _fields_ = [("M", c_int), ("order", c_int), ("problems", c_int), ("team_width", c_int),
                 ("grid", c_int), ("unit_order", c_int), ("split", c_int), ("block_ms", c_double),
-                ("kernel", c_int)]
+                ("kernel", c_int), ("rows_per_sync", c_int)]
 
 
 _PP = ctypes.POINTER(c_void_p)
@@ -367,10 +367,10 @@ class Batch:
         self._chk(load().nrxx_batch_get_tuning(self.h, group, ctypes.byref(t)))
         return {k: getattr(t, k) for k, _ in BatchTuning._fields_}
 
-    def set_tuning(self, group, team_width, grid, unit_order, split=1, kernel=0):
+    def set_tuning(self, group, team_width, grid, unit_order, split=1, kernel=0, rows_per_sync=1):
         t = BatchTuning()
         t.team_width, t.grid, t.unit_order, t.split = team_width, grid, unit_order, split
-        t.kernel = kernel
+        t.kernel, t.rows_per_sync = kernel, rows_per_sync
         self._chk(load().nrxx_batch_set_tuning(self.h, group, ctypes.byref(t)))
 
     def autotune(self, states):

@@ -38,9 +38,14 @@ def state_err(a, b, M):
     return float(max(eu, et, ef))
 
 
-def record_err(a, b):
+def record_err(a, b, floor=1e-3):
     """Residual-type records: basis parameters must agree; coefficients are
-    compared normwise (max abs difference / max abs value)."""
+    compared cell by cell, each difference divided by the largest coefficient
+    of that cell's reference record (bounded below by `floor` times the
+    largest of the whole level, so that a cell whose residual vanishes is
+    compared at the level's scale rather than at zero)."""
     eb = np.abs(a[..., :3] - b[..., :3]).max()
-    ec = np.abs(a[..., 3:] - b[..., 3:]).max() / max(np.abs(b[..., 3:]).max(), 1e-300)
+    cell = np.abs(b[..., 3:]).max(axis=-1, keepdims=True)
+    scale = np.maximum(cell, max(floor * float(cell.max()), 1e-300))
+    ec = (np.abs(a[..., 3:] - b[..., 3:]) / scale).max()
     return float(max(eb, ec))

@@ -32,14 +32,15 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_record_stride():
-    for M in range(3, 9):
+    for M in range(3, 11):
         s = N.record_stride(M)
         assert s >= I.nalpha(M) + 3 and s % 8 == 0 and s - (I.nalpha(M) + 3) < 8
-    assert N.record_stride(2) == -1 and N.record_stride(9) == -1
+    assert N.record_stride(2) == -1 and N.record_stride(11) == -1
 
 
 @pytest.mark.parametrize("bad", [
-    dict(M=2), dict(M=9), dict(nx=31), dict(levels=6), dict(order=3), dict(collision=-1),
+    dict(M=2), dict(M=11), dict(M=10, precision=1), dict(M=9, schedule=1), dict(M=10, schedule=2),
+    dict(nx=31), dict(levels=6), dict(order=3), dict(collision=-1),
     dict(Kn=0.0), dict(wall_theta=[1.0, 0.0, 1.0, 1.0]), dict(gamma=0), dict(precision=7),
     dict(collision=3), dict(collision=2, Pr=0.0),
     dict(limiter=5), dict(nx=4, ny=4, levels=3), dict(schedule=4),
@@ -67,7 +68,7 @@ def test_null_arguments():
     [dict(), dict(s1=3)],                              # smoothing steps must be shared
     [dict(), dict(gamma=2)],                           # so must the cycle type
     [dict(), dict(precision=1)],                       # batches are FP64
-    [dict(), dict(M=9)],                               # invalid member
+    [dict(), dict(M=11)],                              # invalid member
 ])
 def test_batch_create_rejects_invalid_sets_before_touching_the_gpu(bad):
     L = N.load()
@@ -96,7 +97,7 @@ def test_noalloc_residual_checks_arguments_on_the_host():
     nrm = ctypes.c_double(7.0)
     fake = ctypes.c_void_p(256)
     assert L.nrxx_residual_noalloc(None, 0, fake, None, None, None, ctypes.byref(nrm), None) == N.NRXX_EINVAL
-    bad = N.problem(I.spec("lid32_bgk_m3", M=9))
+    bad = N.problem(I.spec("lid32_bgk_m3", M=11))
     assert L.nrxx_residual_noalloc(ctypes.byref(bad), 0, fake, None, None, None, ctypes.byref(nrm), None) == N.NRXX_EINVAL
     ok = N.problem(I.spec("lid32_bgk_m3"))
     assert L.nrxx_residual_noalloc(ctypes.byref(ok), 2, fake, None, None, None, ctypes.byref(nrm), None) == N.NRXX_EINVAL

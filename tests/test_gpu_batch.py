@@ -85,17 +85,60 @@ def test_wavefront_kernel_sweeps_bitwise_equal_single_problem_sweeps():
     st0 = random_states(b, specs, 33)
     want = single_results(specs, st0, lambda c, d: c.sweep(d, nsteps=2))
     full = [b.tuning(g)["grid"] for g in range(b.groups())]
-    for grid in (None, 1, 3):
-        for order in (0, 1):
-            for g in range(b.groups()):
-                t = b.tuning(g)
-                b.set_tuning(g, t["team_width"], grid or full[g], order, 1, kernel=1)
-                assert b.tuning(g)["kernel"] == 1
-            print(f"wavefront kernel: grid {grid} order {order}", flush=True)
-            st = [x.clone() for x in st0]
-            b.sweep(st, nsteps=2)
-            for k in range(len(specs)):
-                assert bool((st[k] == want[k]).all()), (k, grid, order)
+    # rows per wait/acquire: 1, a block that does not divide the columns, and
+    # more than a whole column
+    for rows, grid, order in [(1, None, 0), (1, None, 1), (1, 1, 0), (1, 3, 1), (3, None, 0),
+                              (3, 3, 1), (5, 1, 0), (100, None, 1)]:
+        for g in range(b.groups()):
+            t = b.tuning(g)
+            b.set_tuning(g, t["team_width"], grid or full[g], order, 1, kernel=1, rows_per_sync=rows)
+            assert b.tuning(g)["kernel"] == 1 and b.tuning(g)["rows_per_sync"] == rows
+        print(f"wavefront kernel: rows {rows} grid {grid} order {order}", flush=True)
+        st = [x.clone() for x in st0]
+        b.sweep(st, nsteps=2)
+        for k in range(len(specs)):
+            assert bool((st[k] == want[k]).all()), (k, rows, grid, order)
+
+
+def test_batch_above_the_team_order_bitwise_equals_single_problems():
+    # M = 9 and 10 run on the wavefront-per-cell kernel only, in batches as
+    # for one problem; the cell-team kernel is refused for them
+    require_gpu()
+    from paper_2206_13164_amd import nrxx as N
+    base = dict(wall_u=[0.1, -0.15, 0.35, 0.05], wall_theta=[1.6, 1.0, 0.9, 1.2])
+    specs = [
+        I.spec(None, M=10, collision=1, Pr=2.0 / 3.0, order=1, nx=16, ny=12, Kn=0.3, levels=2, **base),
+        I.spec(None, M=9, collision=2, Pr=2.0 / 3.0, beta=2.0 / 3.0, order=2, limiter=1, nx=12,
+               ny=12, Kn=0.2, levels=2, **base),
+        I.spec(None, M=10, collision=1, Pr=2.0 / 3.0, order=1, nx=8, ny=16, Kn=0.6, levels=1, **base),
+        I.spec(None, M=5, collision=1, Pr=2.0 / 3.0, order=2, limiter=0, nx=16, ny=16, Kn=0.1,
+               levels=2, **base),
+    ]
+    b = N.Batch(specs)
+    assert b.groups() == 3  # (M, order) = (10, 1), (9, 2), (5, 2)
+    for g in range(b.groups()):
+        t = b.tuning(g)
+        if t["M"] > 8:
+            assert t["kernel"] == 1
+            with pytest.raises(N.NrxxError):
+                b.set_tuning(g, 4, t["grid"], t["unit_order"], t["split"], kernel=0)
+    st0 = random_states(b, specs, 71)
+    want = single_results(specs, st0, lambda c, d: c.sweep(d, nsteps=2))
+    st = [x.clone() for x in st0]
+    b.sweep(st, nsteps=2)
+    for k in range(len(specs)):
+        assert bool((st[k] == want[k]).all()), k
+    want_norms = []
+
+    def one(ctx, d):
+        want_norms.append(ctx.fas_vcycle(d))
+
+    want = single_results(specs, st0, one)
+    st = [x.clone() for x in st0]
+    got_norms = b.vcycle(st)
+    for k in range(len(specs)):
+        assert bool((st[k] == want[k]).all()), k
+    assert np.array_equal(got_norms, np.array(want_norms))
 
 
 @pytest.mark.parametrize("kernel", [0, 1])
@@ -164,6 +207,40 @@ def test_batch_solve_masks_graph_replays_and_cycle_counts():
         assert h1[-1] == nrm[k]
     ms, cells = b.stats(reset=True)
     assert ms > 0 and cells > 0
+
+
+def test_batch_solve_matches_the_oracle(orc):
+    # every problem of a batch solved to 1e-8 equals the FP64 oracle run for
+    # the same number of V-cycles (+ mass correction) from the same start
+    require_gpu()
+    from gpu_common import TOL_CONVERGED, state_err
+    from paper_2206_13164_amd import nrxx as N
+    specs = [
+        I.spec("lid32_bgk_m3", nx=16, ny=16),
+        I.spec("lid32_bgk_m3", Kn=0.02),
+        I.spec("paper_table1_32", nx=16, ny=16, levels=2),
+        I.spec("lid128_shakhov_m5_central", nx=16, ny=16, levels=2),
+        I.spec("esbgk64_m5_kn01", nx=16, ny=16, levels=2),
+    ]
+    b = N.Batch(specs)
+    st = b.empty_states()
+    b.init_maxwellian(st)
+    rc, cyc, nrm, ref = b.solve(st, 1e-8, 80, use_graph=True)
+    assert rc == N.NRXX_OK
+    orc.set_threads(8)
+    try:
+        for k, s in enumerate(specs):
+            P = orc.problem(s)
+            w = I.maxwellian_state(s)
+            for _ in range(int(cyc[k])):
+                orc.vcycle(P, w)
+                orc.mass_fix(P, w)
+            got = st[k].cpu().numpy()[..., : w.shape[-1]]
+            err = state_err(got, w, s["M"])
+            print(f"problem {k}: {int(cyc[k])} cycles, field error vs oracle {err:.2e}")
+            assert err < TOL_CONVERGED, (k, err)
+    finally:
+        orc.set_threads(1)
 
 
 def test_batch_autotune_restores_states_and_keeps_results():

@@ -74,6 +74,34 @@ def test_mixed_heated_cavity_reduced(schedule):
     assert err < 1e-6 and mir < 1e-6
 
 
+def test_mixed_heated_cavity_matches_fp64_oracle(orc):
+    # config-3 physics (bottom-heated, Shakhov, Kn 0.05, M = 8, central
+    # slopes) on 16x16 with 2 levels: the FP32-block solve to 1e-9 against
+    # the FP64 oracle solved to 1e-11; the error is the FP32 blocks' own
+    # (the FP64 GPU path equals the oracle to 1e-10, test_gpu_parity.py)
+    require_gpu()
+    s = I.spec("heated256_shakhov_m8_kn005", nx=16, ny=16, levels=2)
+    P = orc.problem(s)
+    orc.set_threads(8)
+    try:
+        want = I.maxwellian_state(s)
+        rc, c64, _ = orc.solve(P, want, 1e-11, 200)
+    finally:
+        orc.set_threads(1)
+    assert rc == 0
+    ctx = context(dict(s, precision=1))
+    d = ctx.empty(0)
+    ctx.init_maxwellian(d)
+    rc, cyc, hist = ctx.solve(d, 1e-9, 200)
+    assert rc == 0, hist
+    got = ctx.to_host(d, want.shape[-1])
+    err = state_err(got, want, 8)
+    print(f"mixed heated 16x16 M=8: {cyc} cycles to 1e-9 (oracle {c64} to 1e-11), "
+          f"field error vs FP64 oracle {err:.2e}, mirror {mirror_err(got, 8):.2e}")
+    assert err < 1e-7
+    assert mirror_err(got, 8) < 1e-7
+
+
 def test_mixed_schedules_agree_bitwise():
     # FP32 queue, static persistent and per-diagonal sweeps give identical blocks
     require_gpu()

@@ -55,6 +55,35 @@ def test_forward_matches_reference(rows):
     assert err < 2e-3
 
 
+def forward_bf16_operands(params, Xs):
+    """The reference forward pass with every product's operands rounded to
+    BF16 as the kernels feed them to the matrix cores (weights are BF16
+    already): inputs and hidden activations rounded before each product,
+    everything else FP64."""
+    a = bf16_round(Xs)
+    for k, (W, b) in enumerate(params):
+        z = a @ W.T + b
+        a = z if k == len(params) - 1 else bf16_round(R.silu(z))
+    return a
+
+
+@pytest.mark.parametrize("rows", [37, 4096])
+def test_forward_elementwise_matches_bf16_operand_reference(rows):
+    # element by element: what is left is FP32 accumulation order and the
+    # rare BF16 rounding flip of a hidden activation that sits on a rounding
+    # boundary (one BF16 ulp, 2^-8, in one term of a 256-term product)
+    torch = require_gpu()
+    m, params, X, T, Xs, Ts, sc = setup(rows, seed=7)
+    Y = m.forward(torch.from_numpy(X).cuda()).cpu().numpy().astype(np.float64)
+    want = forward_bf16_operands(params, Xs) * sc[3] + sc[2]
+    # per output field, errors in units of that field's output scale
+    e = np.abs(Y - want) / (np.abs(want) + sc[3])
+    print(f"rows {rows}: element-wise error median {np.median(e):.2e}, 99.9% {np.quantile(e, 0.999):.2e}, "
+          f"max {e.max():.2e}")
+    assert np.median(e) < 1e-5
+    assert e.max() < 2e-3
+
+
 def test_gradients_match_reference():
     torch = require_gpu()
     m, params, X, T, Xs, Ts, _ = setup(1000, seed=2)

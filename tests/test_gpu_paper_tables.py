@@ -1,8 +1,9 @@
 """GPU: iteration counts of the paper's solver tables (Sec. 4), which belong
 to the method, not to the machine.  Each expected count is the paper's
-(Table 1: single lid, Kn 0.1, 32x32; Table 6: four-sided lid, Kn 0.777,
-64x64; Table 8: bottom-heated, Kn 0.3, 64x64; all Shakhov, M = 5, first
-order, Tol 1e-8, coarsest grid 8x8)."""
+(Table 1: single lid, Kn 0.1, 32x32; Table 3: single lid, M = 10, 64x64;
+Table 4: ES-BGK; Table 6: four-sided lid, Kn 0.777, 64x64; Table 8:
+bottom-heated, Kn 0.3, 64x64; Table 9: second order; Shakhov and M = 5
+unless stated, Tol 1e-8, coarsest grid 8x8)."""
 import pytest
 
 from gpu_common import require_gpu
@@ -11,14 +12,73 @@ from paper_2206_13164_amd import paper_tables as T
 pytestmark = pytest.mark.gpu
 
 
-def row(table, side):
+def row(table, side, kn=None, M=5):
     for t, label, kw, paper in T.ROWS:
-        if t == table and kw["nx"] == side:
+        if (t == table and kw["nx"] == side and (kn is None or kw["Kn"] == kn)
+                and kw.get("M", 5) == M):
             return T.row_spec(kw), paper
-    raise KeyError((table, side))
+    raise KeyError((table, side, kn, M))
 
 
-@pytest.mark.parametrize("table,side", [("1", 32), ("6", 64), ("8", 64), ("9", 32)])
+def test_esbgk_kn1_nmg_iterations_match_the_paper():
+    # Table 4, ES-BGK, Kn 1.0, 64x64, M = 5: 19 NMG iterations in the paper
+    require_gpu()
+    s, paper = row("4", 64, kn=1.0)
+    r = T.solver_run(s, 200)
+    print(f"table 4 (Kn 1.0), 64x64: NMG {r['iterations']} (paper {paper[2]})")
+    assert r["converged"]
+    assert abs(r["iterations"] - paper[2]) <= 2
+
+
+@pytest.mark.parametrize("table,kn", [("3", 0.1), ("3", 1.0), ("4", 0.1), ("4", 1.0)])
+def test_m10_nmg_iterations_match_the_paper(table, kn):
+    # Tables 3 (Shakhov) and 4 (ES-BGK), 64x64, M = 10: NMG 17 / 23 and
+    # 17 / 27 iterations in the paper at Kn 0.1 / 1.0
+    require_gpu()
+    s, paper = row(table, 64, kn=kn, M=10)
+    r = T.solver_run(s, 200)
+    print(f"table {table} (Kn {kn}, M = 10), 64x64: NMG {r['iterations']} (paper {paper[2]}), "
+          f"{r['seconds']:.2f} s", flush=True)
+    assert r["converged"]
+    assert abs(r["iterations"] - paper[2]) <= 2
+
+
+# Rows whose counts deviate from the paper's (measured on the GPU): on the
+# single lid the explicit-Euler and fast-sweeping counts are about 1.2 times
+# the paper's at every grid and Kn, and the NMG count at 256x256, Kn 1.0 is
+# 38 against 27; the four-sided and bottom-heated rows of the same code match.
+# The cause (a detail of the single-lid setup the paper states differently)
+# is not isolated; these tests track the gap.
+@pytest.mark.xfail(reason="single-lid FS count 279 vs the paper's 231 (1.21x), cause not isolated",
+                   strict=True)
+def test_single_lid_fast_sweeping_iterations_match_the_paper():
+    require_gpu()
+    s, paper = row("1", 32)
+    fs = T.solver_run(dict(s, levels=1, s3=1), 2000)
+    print(f"single lid 32x32 Kn 0.1: FS {fs['iterations']} (paper {paper[1]})")
+    assert abs(fs["iterations"] - paper[1]) <= 0.05 * paper[1]
+
+
+@pytest.mark.xfail(reason="single-lid Euler count 2205 vs the paper's 1823 (1.21x), cause not isolated",
+                   strict=True)
+def test_single_lid_euler_iterations_match_the_paper():
+    require_gpu()
+    s, paper = row("1", 32)
+    eu = T.euler_run(s, 10000)
+    print(f"single lid 32x32 Kn 0.1: Euler {eu['iterations']} (paper {paper[0]})")
+    assert abs(eu["iterations"] - paper[0]) <= 0.05 * paper[0]
+
+
+@pytest.mark.xfail(reason="NMG at 256x256, Kn 1.0: 38 iterations vs the paper's 27", strict=True)
+def test_single_lid_nmg_256_kn1_iterations_match_the_paper():
+    require_gpu()
+    s, paper = row("2", 256)
+    r = T.solver_run(s, 200)
+    print(f"single lid 256x256 Kn 1.0: NMG {r['iterations']} (paper {paper[2]})")
+    assert abs(r["iterations"] - paper[2]) <= 2
+
+
+@pytest.mark.parametrize("table,side", [("1", 32), ("6", 64), ("8", 64), ("9", 32), ("4", 64)])
 def test_nmg_iterations_match_the_paper(table, side):
     require_gpu()
     s, paper = row(table, side)

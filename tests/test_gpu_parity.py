@@ -15,7 +15,13 @@ CASES = [
     (6, 1, 1, 0), (7, 1, 2, 0), (8, 1, 2, 0), (8, 1, 1, 0),
     # ES-BGK (collision 2)
     (3, 2, 1, 0), (5, 2, 2, 1), (8, 2, 2, 0),
+    # past the cell team's largest order: one wavefront per cell
+    (9, 1, 2, 0), (10, 1, 1, 0), (10, 0, 2, 0), (10, 2, 2, 1),
 ]
+
+
+def cid(case):
+    return "M{}-c{}-o{}-l{}".format(*case)
 
 
 def small_spec(M, collision, order, limiter, **kw):
@@ -26,7 +32,7 @@ def small_spec(M, collision, order, limiter, **kw):
     return I.spec(None, **d)
 
 
-@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("case", CASES, ids=cid)
 def test_residual_matches_oracle(orc, case):
     require_gpu()
     s = small_spec(*case)
@@ -47,7 +53,7 @@ def test_residual_matches_oracle(orc, case):
     assert np.all(got[..., 3:][..., odd] == 0.0)
 
 
-@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("case", CASES, ids=cid)
 def test_sweep_matches_oracle(orc, case):
     require_gpu()
     s = small_spec(*case)
@@ -63,7 +69,7 @@ def test_sweep_matches_oracle(orc, case):
         assert state_err(got, want, s["M"]) < TOL_STEP, mask
 
 
-@pytest.mark.parametrize("case", [(5, 1, 2, 0), (3, 0, 1, 0), (8, 1, 2, 0)])
+@pytest.mark.parametrize("case", [(5, 1, 2, 0), (3, 0, 1, 0), (8, 1, 2, 0), (10, 1, 2, 0)], ids=cid)
 def test_coarse_sweep_with_rhs_matches_oracle(orc, case):
     require_gpu()
     s = small_spec(*case)
@@ -78,7 +84,7 @@ def test_coarse_sweep_with_rhs_matches_oracle(orc, case):
     assert state_err(ctx.to_host(d, st.shape[-1]), want, s["M"]) < TOL_STEP
 
 
-@pytest.mark.parametrize("case", [(5, 1, 2, 0), (3, 0, 1, 0), (8, 1, 2, 0)])
+@pytest.mark.parametrize("case", [(5, 1, 2, 0), (3, 0, 1, 0), (8, 1, 2, 0), (10, 1, 2, 0)], ids=cid)
 def test_transfer_operators_match_oracle(orc, case):
     require_gpu()
     s = small_spec(*case)
@@ -111,6 +117,7 @@ def test_transfer_operators_match_oracle(orc, case):
     ("lid32_bgk_m3", {}),
     ("lid128_shakhov_m5", dict(nx=32, ny=32, levels=3)),
     ("heated256_shakhov_m8_kn02", dict(nx=16, ny=16, levels=2)),
+    ("lid128_shakhov_m5", dict(nx=16, ny=16, levels=2, M=10)),
 ])
 def test_vcycle_matches_oracle(orc, name, kw):
     require_gpu()
@@ -176,6 +183,51 @@ def test_converged_fields_match_oracle_config2_reduced(orc):
     d = ctx.to_device(I.maxwellian_state(s))
     ctx.solve(d, 0.0, n, ref_norm=r0)
     assert state_err(ctx.to_host(d, st.shape[-1]), st, s["M"]) < TOL_CONVERGED
+
+
+@pytest.mark.parametrize("case", [(3, 0, 1, 0), (5, 1, 2, 1)], ids=cid)
+def test_w_cycle_matches_oracle(orc, case):
+    # gamma = 2 (Alg. 2 with two recursive calls per level): two W-cycles on
+    # three levels
+    require_gpu()
+    s = small_spec(*case, nx=16, ny=16, lx=1.0, ly=1.0, levels=3, gamma=2)
+    P = orc.problem(s)
+    ctx = context(s)
+    st = I.maxwellian_state(s)
+    d = ctx.to_device(st)
+    for _ in range(2):
+        orc.vcycle(P, st)
+        orc.mass_fix(P, st)
+        gn = ctx.fas_vcycle(d)
+        assert state_err(ctx.to_host(d, st.shape[-1]), st, s["M"]) < TOL_STEP
+    _, wn = orc.residual(P, 0, st)
+    assert abs(gn - wn) < 1e-10 * wn
+
+
+def test_converged_fields_match_oracle_central_slopes_reduced(orc):
+    # the single-cavity bench workload's physics (Shakhov Pr 2/3, Kn 0.075,
+    # M = 5, the paper's central slopes, lid 0.5) on 32x32 with 3 levels,
+    # 16 V-cycles from the Maxwellian on both sides
+    require_gpu()
+    s = I.spec("lid128_shakhov_m5_central", nx=32, ny=32, levels=3)
+    P = orc.problem(s)
+    st = I.maxwellian_state(s)
+    n = 16
+    orc.set_threads(8)
+    try:
+        _, r0 = orc.residual(P, 0, st)
+        rc, cyc, hist = orc.solve(P, st, 0.0, n, ref_norm=r0)
+    finally:
+        orc.set_threads(1)
+    ctx = context(s)
+    d = ctx.to_device(I.maxwellian_state(s))
+    rcg, cg, hg = ctx.solve(d, 0.0, n, ref_norm=r0)
+    assert cg == cyc == n
+    err = state_err(ctx.to_host(d, st.shape[-1]), st, s["M"])
+    print(f"central slopes, 32x32, {n} V-cycles: field error {err:.2e}, "
+          f"relative residual {hist[-1] / r0:.2e}")
+    assert err < TOL_CONVERGED
+    assert np.max(np.abs(hg - hist)) < 1e-12 * hist[0]
 
 
 @pytest.mark.parametrize("name", ["lid128_shakhov_m5", "heated256_shakhov_m8_kn005"])
@@ -275,7 +327,7 @@ def test_mass_and_init(orc):
     assert abs(ctx.mass(ctx.to_device(st)) - orc.mass(P, 0, st)) < 1e-14
 
 
-@pytest.mark.parametrize("case", [(3, 0, 1, 0), (5, 1, 2, 0), (5, 1, 2, 1), (8, 1, 2, 0)])
+@pytest.mark.parametrize("case", [(3, 0, 1, 0), (5, 1, 2, 0), (5, 1, 2, 1), (8, 1, 2, 0)], ids=cid)
 def test_persistent_and_diagonal_schedules_agree_bitwise(orc, case):
     # the persistent column-pipelined sweep and the one-launch-per-diagonal
     # sweep must produce identical bits (both are the serial order)
