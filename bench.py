@@ -93,21 +93,26 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def profiled_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` on `workload` from the committed
-    FETCH_SIZE / WRITE_SIZE summary, or None when the summary is missing or
-    was taken on a different kernel source."""
-    path = os.path.join(PROFILES, f"{kernel}_{workload}.md")
+def sweep_traffic(workload: str):
+    """{kernel symbol: HBM bytes per launch} of the batch's sweep kernels
+    from the committed FETCH_SIZE / WRITE_SIZE summary, or None when it is
+    missing or was taken on a different kernel source."""
+    path = os.path.join(PROFILES, f"sweep_traffic_{workload}.md")
     if not os.path.exists(path):
         return None
-    vals = {}
+    out, sha = {}, None
     for line in open(path):
-        if ":" in line and line.startswith("- "):
-            k, v = line[2:].split(":", 1)
-            vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel_source_sha256") != kernel_source_hash() or "traffic_bytes_per_launch" not in vals:
+        if line.startswith("- kernel_source_sha256:"):
+            sha = line.split(":", 1)[1].strip().strip("`")
+        m = line.strip().split("|")
+        if len(m) > 6 and m[1].strip().startswith("`k_"):
+            try:
+                out[m[1].strip().strip("`")] = float(m[-2])
+            except ValueError:
+                pass
+    if sha != kernel_source_hash() or not out:
         return None
-    return float(vals["traffic_bytes_per_launch"])
+    return out
 
 
 def host_cpu():
@@ -146,6 +151,26 @@ def time_to_residual(b, st, max_cycles):
     return ttr, cyc, nrm, ref, rc
 
 
+def apply_tuning(b, tunings):
+    """Set every group's sweep tuning from a list written by --tuning-out
+    (matched by (M, order))."""
+    by = {(t["M"], t["order"]): t for t in tunings}
+    for g in range(b.groups()):
+        cur = b.tuning(g)
+        t = by[(cur["M"], cur["order"])]
+        b.set_tuning(g, t["team_width"], t["grid"], t["unit_order"], t["split"], kernel=t["kernel"],
+                     rows_per_sync=t["rows_per_sync"])
+
+
+def sweep_kernel_name(t):
+    """Kernel symbol (template arguments as rocprofv3 prints them) of a
+    group's sweep tuning."""
+    if t["kernel"] == 1:
+        return f"k_wsweep<{t['M']}, {t['order']}, {2 if t['M'] >= 7 else 4}>"
+    return (f"k_bsweep<double, {t['M']}, {t['order']}, {t['team_width']}, "
+            f"{'true' if t['split'] else 'false'}>")
+
+
 def headline(args):
     import torch
     from paper_2206_13164_amd import inputs as I
@@ -157,9 +182,15 @@ def headline(args):
     st = b.empty_states()
     b.init_maxwellian(st)
     t0 = time.perf_counter()
-    b.autotune(st)
+    if args.tuning_in:
+        apply_tuning(b, json.load(open(args.tuning_in)))
+    else:
+        b.autotune(st)
     tune_s = time.perf_counter() - t0
-    log(f"autotune {tune_s:.1f} s")
+    log(f"autotune {tune_s:.1f} s" if not args.tuning_in else f"tuning read from {args.tuning_in}")
+    if args.tuning_out:
+        with open(args.tuning_out, "w") as fh:
+            json.dump([b.tuning(g) for g in range(b.groups())], fh)
     b.set_timing(True)
     b.init_maxwellian(st)
     b.solve(st, 0.0, max(1, args.warmup), use_graph=False)  # warm-up cycles
@@ -192,7 +223,7 @@ def headline(args):
         tot_flops += fl
         tot_bytes += by
         groups.append({"M": t["M"], "order": t["order"], "problems": t["problems"],
-                       "kernel": "k_wsweep" if t["kernel"] == 1 else "k_bsweep",
+                       "kernel": sweep_kernel_name(t),
                        "team_width": t["team_width"], "grid": t["grid"], "unit_order": t["unit_order"],
                        "split": t["split"], "launches": nl, "avg_launch_us": ms * 1e3 / max(nl, 1),
                        "cell_updates": cf + cc, "achieved_tflops": fl / max(ms, 1e-30) / 1e9,
@@ -204,6 +235,17 @@ def headline(args):
     else:
         ttr, cyc2, nrm2, ref2, rc2 = time_to_residual(b, st, args.max_cycles)
     achieved = tot_flops / max(tot_ms, 1e-30) / 1e9  # TFLOP/s per launch-second
+    # HBM bytes per launch from the committed counter summary, when it was
+    # taken on these kernels (same source, same per-group kernels)
+    tb = sweep_traffic(HEADLINE)
+    traffic = None
+    if tb is not None and all(g["kernel"] in tb for g in groups):
+        traffic = sum(g["launches"] * tb[g["kernel"]] for g in groups) / max(tot_launch, 1)
+    # critical path: the longest chain of dependent cell updates of one
+    # cavity in a cycle (anti-diagonal steps of every directional sweep)
+    chains = [(a["chain"], s) for a, s in zip(acc, specs)]
+    chain, big = max(chains, key=lambda x: x[0])
+    cyc_ms = wall / args.steps * 1e3
 
     gbs = tot_bytes / max(tot_ms, 1e-30) / 1e6
     conv = [bool(nrm2[i] <= 1e-8 * ref2[i]) for i in range(len(nrm2))]
@@ -234,7 +276,20 @@ def headline(args):
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": None,
+            "traffic": traffic,
+            "limiter": "latency of the dependent cell updates, not FP64 issue or HBM bandwidth",
+            "hbm_target": {"frac_wanted": 0.5, "frac": gbs / PEAK_HBM_GBS,
+                           "met": gbs / PEAK_HBM_GBS >= 0.5,
+                           "shortfall_x": 0.5 / max(gbs / PEAK_HBM_GBS, 1e-30)},
+            "critical_path": {
+                "cavity": f"{big['nx']}x{big['ny']}, M = {big['M']}, {big['levels']} levels",
+                "dependent_updates_per_cycle": chain,
+                "cycle_ms": cyc_ms,
+                "us_per_dependent_update_if_chain_bound": cyc_ms * 1e3 / chain,
+                "note": "a cycle can not finish before this chain of dependent cell updates of "
+                        "its largest cavity; us_per_dependent_update_if_chain_bound is the time "
+                        "per link at which the measured cycle would be the chain alone",
+            },
             "kernel": "batched work-queue sweep kernels (k_wsweep: one wavefront per cell, or "
                       "k_bsweep: cell teams, per group as autotuned; up to 8 directional sweeps "
                       "of one level per launch)",
@@ -430,6 +485,9 @@ def main():
     ap.add_argument("--no-ttr", action="store_true",
                     help="skip the batch's time-to-residual solve (profiling runs)")
     ap.add_argument("--single-workload", default="lid128_shakhov_m5_central")
+    ap.add_argument("--tuning-out", default=None, help="write the groups' sweep tunings (JSON)")
+    ap.add_argument("--tuning-in", default=None,
+                    help="take the groups' sweep tunings from a --tuning-out file instead of autotuning")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
