@@ -413,7 +413,7 @@ def learned_leg(draws, max_cycles):
     return {"grid": "256x256", "M": 5, "levels": 6, "tol": 1e-8, "draws": rows,
             "total_seconds_maxwellian_fp64": tot0, "total_seconds_learned_fp32_blocks": tot1,
             "speedup_total": tot0 / tot1,
-            "network": {k: v for k, v in ws.meta.items() if k != "loss"}}
+            "network": {k: v for k, v in ws.meta.items() if k not in ("loss", "validation")}}
 
 
 def single_leg(workload, max_cycles):

@@ -103,7 +103,8 @@ struct nrxx_ctx {
   double *ebuf = nullptr;                // forward Euler: -R of a level (finest-level size)
   std::string err;
   struct Timed { hipEvent_t a, b; double cells, launches; };
-  std::vector<Timed> timed;
+  std::vector<Timed> timed;                               // recorded, not yet read
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;  // read event pairs, for reuse
   double sweep_ms = 0.0, sweep_cells = 0.0, sweep_launches = 0.0;
 };
 
@@ -165,6 +166,50 @@ int check_device(nrxx_ctx *c) {
   return NRXX_OK;
 }
 
+// Sweep timing: an event pair around each smoothing call, taken from the
+// context's pool; finished pairs are read into the running totals and go
+// back to the pool (every 4096 calls, and on nrxx_sweep_stats).
+int timing_begin(nrxx_ctx *c, nrxx_ctx::Timed &tm) {
+  if (!c->ev_free.empty()) {
+    tm.a = c->ev_free.back().first;
+    tm.b = c->ev_free.back().second;
+    c->ev_free.pop_back();
+  } else {
+    CHK(hipEventCreate(&tm.a));
+    if (hipEventCreate(&tm.b) != hipSuccess) {
+      (void)hipEventDestroy(tm.a);
+      return fail(c, NRXX_EHIP, "hipEventCreate failed");
+    }
+  }
+  CHK(hipEventRecord(tm.a, c->stream));
+  return NRXX_OK;
+}
+
+int fold_timings(nrxx_ctx *c) {
+  for (auto &x : c->timed) {
+    float ms = 0.f;
+    CHK(hipEventElapsedTime(&ms, x.a, x.b));
+    c->sweep_ms += ms;
+    c->sweep_cells += x.cells;
+    c->sweep_launches += x.launches;
+    c->ev_free.emplace_back(x.a, x.b);
+  }
+  c->timed.clear();
+  return NRXX_OK;
+}
+
+int timing_end(nrxx_ctx *c, nrxx_ctx::Timed &tm, double cells, double launches) {
+  CHK(hipEventRecord(tm.b, c->stream));
+  tm.cells = cells;
+  tm.launches = launches;
+  c->timed.push_back(tm);
+  if (c->timed.size() > 4096) {
+    CHK(hipEventSynchronize(c->timed.back().b));
+    return fold_timings(c);
+  }
+  return NRXX_OK;
+}
+
 // Directional sweeps of a level through the work-queue kernel: up to
 // kMaxSweepsPerLaunch sweeps per launch, counters cleared by a fill kernel.
 template <typename Real>
@@ -201,9 +246,8 @@ int queue_sweeps(nrxx_ctx *c, int level, Real *st, const Real *rhs, const std::v
 int sweep_impl(nrxx_ctx *c, int level, double *st, const double *rhs, int mask, int nsteps) {
   const LevelArgs &A = c->lv[level];
   nrxx_ctx::Timed tm;
-  CHK(hipEventCreate(&tm.a));
-  CHK(hipEventCreate(&tm.b));
-  CHK(hipEventRecord(tm.a, c->stream));
+  int trc = timing_begin(c, tm);
+  if (trc) return trc;
   int ndir = 0;
   std::vector<int> dirs;
   for (int s = 0; s < nsteps; ++s)
@@ -236,24 +280,7 @@ int sweep_impl(nrxx_ctx *c, int level, double *st, const double *rhs, int mask, 
         launches += 1.0;
       }
   }
-  CHK(hipEventRecord(tm.b, c->stream));
-  tm.cells = (double)ndir * A.nx * A.ny;
-  tm.launches = launches;
-  c->timed.push_back(tm);
-  if (c->timed.size() > 4096) {  // fold finished timings
-    CHK(hipEventSynchronize(c->timed.back().b));
-    for (auto &x : c->timed) {
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, x.a, x.b);
-      c->sweep_ms += ms;
-      c->sweep_cells += x.cells;
-      c->sweep_launches += x.launches;
-      (void)hipEventDestroy(x.a);
-      (void)hipEventDestroy(x.b);
-    }
-    c->timed.clear();
-  }
-  return NRXX_OK;
+  return timing_end(c, tm, (double)ndir * A.nx * A.ny, launches);
 }
 
 // One FP32 smoothing block (precision 1).  The FP64 defect d = r - R64(f0)
@@ -274,9 +301,8 @@ int sweep32_impl(nrxx_ctx *c, int level, double *st, const double *rhs, int mask
       if (mask & (1 << k)) dirs.push_back(k);
   if (dirs.empty()) return NRXX_OK;
   nrxx_ctx::Timed tm;
-  CHK(hipEventCreate(&tm.a));
-  CHK(hipEventCreate(&tm.b));
-  CHK(hipEventRecord(tm.a, c->stream));
+  int trc = timing_begin(c, tm);
+  if (trc) return trc;
   float *g = c->g32[level], *g0 = c->g0_32[level], *r = c->r32[level];
   // d = r - R64(f0) and its norm; s = block scale; s d -> g as a temporary
   // FP32 copy; r32 = R32(g0) + s d; then g = g0
@@ -313,11 +339,7 @@ int sweep32_impl(nrxx_ctx *c, int level, double *st, const double *rhs, int mask
       }
   }
   CHK(launch_from32(c->M, A, st, g, g0, scale, c->derr, c->stream));
-  CHK(hipEventRecord(tm.b, c->stream));
-  tm.cells = (double)dirs.size() * A.nx * A.ny;
-  tm.launches = launches;
-  c->timed.push_back(tm);
-  return NRXX_OK;
+  return timing_end(c, tm, (double)dirs.size() * A.nx * A.ny, launches);
 }
 
 int smooth_impl(nrxx_ctx *c, int level, double *st, const double *rhs, int mask, int nsteps) {
@@ -601,6 +623,10 @@ int nrxx_destroy(nrxx_ctx *c) {
     (void)hipEventDestroy(x.a);
     (void)hipEventDestroy(x.b);
   }
+  for (auto &x : c->ev_free) {
+    (void)hipEventDestroy(x.first);
+    (void)hipEventDestroy(x.second);
+  }
   for (auto *v : {&c->Rbar, &c->fbar, &c->ftil, &c->rhs, &c->RH})
     for (double *p : *v)
       if (p) (void)hipFree(p);
@@ -758,6 +784,10 @@ int nrxx_solve(nrxx_ctx *c, double *state, double tol, int max_cycles, double re
   if (!c) return NRXX_EINVAL;
   if (!state || !cycles_out || max_cycles < 0 || !(tol >= 0))
     return fail(c, NRXX_EINVAL, "bad argument");
+  // FP32 blocks: every solve takes its own first block of each level as
+  // the reference of the block scale, so that equal solves are equal
+  if (c->P.precision == 1)
+    CHK(hipMemsetAsync(c->dblk, 0, sizeof(double) * 2 * c->L, c->stream));
   double nrm;
   int rc = residual_impl(c, 0, state, nullptr, nullptr, &nrm);
   if (rc) return rc;
@@ -789,16 +819,8 @@ int nrxx_sweep_stats(nrxx_ctx *c, double *ms_out, double *cells_out, double *lau
                      int reset) {
   if (!c) return NRXX_EINVAL;
   CHK(hipStreamSynchronize(c->stream));
-  for (auto &x : c->timed) {
-    float ms = 0.f;
-    CHK(hipEventElapsedTime(&ms, x.a, x.b));
-    c->sweep_ms += ms;
-    c->sweep_cells += x.cells;
-    c->sweep_launches += x.launches;
-    (void)hipEventDestroy(x.a);
-    (void)hipEventDestroy(x.b);
-  }
-  c->timed.clear();
+  int rc = fold_timings(c);
+  if (rc) return rc;
   if (ms_out) *ms_out = c->sweep_ms;
   if (cells_out) *cells_out = c->sweep_cells;
   if (launches_out) *launches_out = c->sweep_launches;

@@ -7,7 +7,8 @@ model, Table 4;
 four-sided, Table 6; bottom-heated, Table 8; second order, Table 9).  The iteration counts belong to the
 method and can be compared with the paper's; wall times are this GPU's.
 
-    python -m paper_2206_13164_amd.paper_tables [--min-side 0] [--max-side 128] [--out FILE]
+    python -m paper_2206_13164_amd.paper_tables [--min-side 0] [--max-side 128] [--tables 3,4]
+        [--nmg-only] [--out FILE]
 
 Prints one JSON line per row.
 """
@@ -108,19 +109,25 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--max-side", type=int, default=128)
     ap.add_argument("--min-side", type=int, default=0)
+    ap.add_argument("--tables", default=None, help="comma list of table numbers (default: all)")
+    ap.add_argument("--nmg-only", action="store_true", help="skip the Euler and FS solvers")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
+    tables = set(args.tables.split(",")) if args.tables else None
     import torch
     torch.cuda.set_device(0)
     lines = []
     for table, label, kw, paper in ROWS:
         if kw["nx"] > args.max_side or kw["nx"] < args.min_side:
             continue
+        if tables is not None and table not in tables:
+            continue
         s = row_spec(kw)
         row = {"table": table, "case": label, "paper_iterations": dict(zip(("euler", "fs", "nmg"), paper))}
         row["nmg"] = solver_run(s, 200)
-        row["fs"] = solver_run(dict(s, levels=1, s3=1), 20000)
-        if paper[0] is not None:
+        if not args.nmg_only:
+            row["fs"] = solver_run(dict(s, levels=1, s3=1), 20000)
+        if paper[0] is not None and not args.nmg_only:
             row["euler"] = euler_run(s, 100000)
         lines.append(json.dumps(row))
         print(lines[-1], flush=True)

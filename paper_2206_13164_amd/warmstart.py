@@ -10,6 +10,10 @@ and keeps the bookkeeping.
 
 Command line (writes the weights file used by tests and the benchmark):
     python -m paper_2206_13164_amd.warmstart train --draws 2000 --out FILE
+    python -m paper_2206_13164_amd.warmstart validate --draws 16
+The second solves validation draws (never trained on) from the Maxwellian
+and from the prediction and stores the Kn gate above which the prediction
+is not used.
 """
 from __future__ import annotations
 
@@ -145,12 +149,15 @@ class WarmStart:
     """A trained network loaded into the library, and the warm-started
     initialisation with the Maxwellian fallback."""
 
-    def __init__(self, path=DEFAULT_WEIGHTS, max_rows=FIELD_GRID * FIELD_GRID):
+    def __init__(self, path=DEFAULT_WEIGHTS, max_rows=FIELD_GRID * FIELD_GRID, gate=True):
         z = np.load(path, allow_pickle=False)
         self.m = N.Mlp([int(w) for w in z["widths"]], max_rows=max_rows)
         self.m.set_params(z["params"])
         self.m.set_scaling(z["in_mean"], z["in_std"], z["out_mean"], z["out_std"])
         self.meta = json.loads(bytes(z["meta"]).decode())
+        # Kn from which the prediction is not used (set by `validate`): above
+        # it the V-cycle's asymptotic rate, not the start, sets the cycles
+        self.kn_gate = self.meta.get("kn_gate") if gate else None
 
     def fields(self, spec):
         """Predicted fields on the field grid of the cavity: (fny, fnx, 9)."""
@@ -161,8 +168,12 @@ class WarmStart:
 
     def apply(self, ctx, state, spec, maxwellian_norm):
         """Fill `state` from the prediction; fall back to the global
-        Maxwellian if the prediction is non-physical or its residual norm is
-        not below the Maxwellian's.  Returns (used, norm of the start)."""
+        Maxwellian if Kn is at or above the validated gate, if the prediction
+        is non-physical or if its residual norm is not below the
+        Maxwellian's.  Returns (used, norm of the start)."""
+        if self.kn_gate is not None and spec["Kn"] >= self.kn_gate:
+            ctx.init_maxwellian(state)
+            return "maxwellian", maxwellian_norm
         try:
             ctx.init_fields(state, self.fields(spec))
             nw = ctx.residual(state)
@@ -204,9 +215,49 @@ def compare(spec, ws, tol=1e-8, max_cycles=200, precision=(0, 1)):
     return out
 
 
+def validation_draws(n, after=2000, side=256, levels=6):
+    """Draws after[..after+n] of the training stream (rng(SEED_TRAIN), the
+    training set's draw order), never used in training, at side^2 cells and
+    M = 5."""
+    d = I.cavity_draws(after + n, I.SEED_TRAIN, sides=(FIELD_GRID,), levels=TRAIN_LEVELS,
+                       tol=TRAIN_TOL)[after:]
+    return [dict(s, nx=side, ny=side, M=5, levels=levels, tol=1e-8) for s in d]
+
+
+def choose_gate(rows):
+    """Smallest validation Kn at which the learned start saved no cycle
+    (None when it saved cycles on every draw)."""
+    bad = [r["Kn"] for r in rows if r["learned"] >= r["maxwellian"]]
+    return min(bad) if bad else None
+
+
+def validate(path, n, log=print):
+    """Solve n validation draws from the Maxwellian and from the (ungated)
+    prediction, choose the Kn gate and store it in the weights file."""
+    ws = WarmStart(path, gate=False)
+    rows = []
+    for s in validation_draws(n):
+        r = compare(s, ws, tol=1e-8, precision=(0,))
+        rows.append(dict(Kn=s["Kn"], lid=s["wall_u"][2], maxwellian=r["maxwellian_p0"]["cycles"],
+                         learned=r["learned_p0"]["cycles"]))
+        log(json.dumps(rows[-1]))
+    gate = choose_gate(rows)
+    z = dict(np.load(path, allow_pickle=False))
+    meta = json.loads(bytes(z["meta"]).decode())
+    meta["kn_gate"] = gate
+    meta["validation"] = rows
+    z["meta"] = np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8)
+    np.savez(path, **z)
+    log(json.dumps({"kn_gate": gate}))
+    return gate, rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
+    v = sub.add_parser("validate")
+    v.add_argument("--draws", type=int, default=16)
+    v.add_argument("--weights", default=DEFAULT_WEIGHTS)
     t = sub.add_parser("train")
     t.add_argument("--draws", type=int, default=2000)
     t.add_argument("--epochs", type=int, default=20)
@@ -217,6 +268,9 @@ def main():
     import torch
     torch.cuda.set_device(0)
     log = lambda s: print(s, flush=True)
+    if args.cmd == "validate":
+        validate(args.weights, args.draws, log=log)
+        return
     t0 = time.perf_counter()
     X, T, info = training_set(args.draws, log=log)
     t1 = time.perf_counter()
