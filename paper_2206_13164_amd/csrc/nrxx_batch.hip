@@ -131,7 +131,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__
         cell_team<Real, M, ORDER, NW, MODE_SWEEP>(sA, lds, st, rhs, nullptr, nullptr, nullptr, i, j,
                                                   err, NoWait(), HOIST_SLOTS ? &slots : nullptr);
         if (threadIdx.x == 0)
-          __hip_atomic_store(cs + i, b + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          publish(cs + i, b + 1);  // wavefront 0 stored the cell
         __syncthreads();
         continue;
       }
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_bsweep(const BLevel *__restrict__
         return;  // uniform across the team
       }
       if (threadIdx.x == 0)
-        __hip_atomic_store(cs + i, b + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        publish(cs + i, b + 1);  // wavefront 0 stored the cell
       __syncthreads();
     }
   }

@@ -233,9 +233,31 @@ __device__ __forceinline__ void get_slots(const Real *buf, int lane, Real (&v)[G
   for (int r = 0; r < G<M>::SL; ++r) v[r] = buf[lane + WAVE * r];
 }
 
+// Publishing a cell to the other workgroups of a sweep.  Each XCD has its
+// own L2, so an agent-scope release fence writes back every dirty line of
+// the XCD's L2 (buffer_wbl2) before the flag store; with thousands of
+// wavefronts each releasing a cell every few microseconds that write-back
+// dominated the sweep (2.6x slower at M = 5).  The records a sweep publishes
+// are instead stored with agent-scope atomic stores, which are performed at
+// the device's coherence point when they complete, so the flag store only has
+// to follow the completion of this wavefront's stores: the release sequence
+// without the write-back.  Readers keep the agent-scope acquire.
+template <typename Real>
+__device__ __forceinline__ void put_shared(Real *p, Real v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sets *flag = value once every store this wavefront issued before has
+// completed (the cell's record was written with put_shared).  Called by the
+// wavefront that stored the record.
+__device__ __forceinline__ void publish(int *flag, int value) {
+  __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+  __hip_atomic_store(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Coalesced write of a full record from (params, LDS cube); odd-alpha_3
 // coefficients are written as zeros.
-template <typename Real, int M>
+template <typename Real, int M, bool SHARED = false>
 __device__ __forceinline__ void store_record(Real *__restrict__ rec, Real u1, Real u2,
                                              Real th, const Real *cube, int lane) {
   using g = G<M>;
@@ -252,7 +274,8 @@ __device__ __forceinline__ void store_record(Real *__restrict__ rec, Real u1, Re
         int a1 = c_canon.a1[al], a2 = c_canon.a2[al], a3 = c_canon.a3[al];
         x = (a3 & 1) ? Real(0.0) : cube[a1 + g::D1 * a2 + g::D2 * (a3 >> 1)];
       }
-      rec[v] = x;
+      if constexpr (SHARED) put_shared(rec + v, x);
+      else rec[v] = x;
     }
   }
 }
@@ -971,7 +994,8 @@ __device__ bool cell_team(const LevelArgs &A, Real *lds, Real *__restrict__ st,
       for (int r = 0; r < g::SL; ++r) fs[r] = c.f[r] + dt * (rr ? R[r] - rv[r] : R[r]);
       Cell<Real, M> nc;
       if (normalise<Real, M>(c.u1, c.u2, c.th, fs, W, nc))
-        store_record<Real, M>(const_cast<Real *>(recp<Real, M>(A, st, i, j)), nc.u1, nc.u2, nc.th, W.bA, lane);
+        store_record<Real, M, true>(const_cast<Real *>(recp<Real, M>(A, st, i, j)), nc.u1, nc.u2,
+                                    nc.th, W.bA, lane);
       else if (lane == 0)
         atomicOr(err, 1);
     } else {
@@ -1041,9 +1065,11 @@ __device__ __forceinline__ bool wait_at_least(const int *flag, int target, int *
   }
 }
 
-// Makes the stores published (released) by the teams whose flags were
-// observed visible to the loads that follow.
+// Makes the stores published by the teams whose flags were observed visible
+// to the loads that follow (agent-scope acquire: invalidates this XCD's
+// caches of non-coherent lines).
 __device__ __forceinline__ void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
 
 // Table slot of a group's cell (entries sorted by their first cell).
 __device__ __forceinline__ int find_slot(const BLevel *__restrict__ tab, int nslot, int cell) {

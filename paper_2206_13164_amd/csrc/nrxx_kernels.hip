@@ -86,8 +86,8 @@ __global__ __launch_bounds__(NW * WAVE) void k_sweep_persist(
         return;  // uniform across the team
       }
       if (threadIdx.x == 0) {
-        // wavefront 0 stored the cell; publish it (agent-scope release)
-        __hip_atomic_store(cnt + i, sbase + b + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        // wavefront 0 stored the cell; publish it
+        publish(cnt + i, sbase + b + 1);
       }
       __syncthreads();
     }

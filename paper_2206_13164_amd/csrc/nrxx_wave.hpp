@@ -576,7 +576,7 @@ __device__ bool wnormalise(Real ou1, Real ou2, Real oth, const Real (&fs)[G<M>::
 
 // Coalesced write of a full record from (params, X in L1); odd-alpha_3
 // coefficients as zeros.
-template <typename Real, int M>
+template <typename Real, int M, bool SHARED = false>
 __device__ __forceinline__ void wstore_record(Real *__restrict__ rec, Real u1, Real u2, Real th,
                                               const Real *X, const WTabs<M> &T, int lane) {
   using g = G<M>;
@@ -592,7 +592,8 @@ __device__ __forceinline__ void wstore_record(Real *__restrict__ rec, Real u1, R
         const int q = T.canon1[v - 3];
         x = q < 0 ? Real(0.0) : X[q];
       }
-      rec[v] = x;
+      if constexpr (SHARED) put_shared(rec + v, x);
+      else rec[v] = x;
     }
   }
 }
@@ -837,8 +838,8 @@ __device__ void wave_cell(const LevelArgs &A, Real *lw, const WTabs<M> &T, const
     for (int r = 0; r < g::SL; ++r) fs[r] = c.f[r] + dt * (rr ? R[r] - rv[r] : R[r]);
     Cell<Real, M> nc;
     if (wnormalise<Real, M>(c.u1, c.u2, c.th, fs, lw, S, lane, nc))
-      wstore_record<Real, M>(const_cast<Real *>(recp<Real, M>(A, st, i, j)), nc.u1, nc.u2, nc.th,
-                             lw + L::X, T, lane);
+      wstore_record<Real, M, true>(const_cast<Real *>(recp<Real, M>(A, st, i, j)), nc.u1, nc.u2,
+                                   nc.th, lw + L::X, T, lane);
     else if (lane == 0)
       atomicOr(err, 1);
   } else {

@@ -131,7 +131,7 @@ void k_wsweep(const BLevel *__restrict__ tab, const int *__restrict__ units, int
         const int j = jrev ? ny - 1 - b : b;
         wave_cell<double, M, ORDER>(A, lw, sh.tabs, S, lane, st, rhs, i, j, err);
       }
-      if (lane == 0) __hip_atomic_store(cs + i, b1 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0) publish(cs + i, b1 + 1);
     }
   }
 }
