@@ -136,15 +136,17 @@ void k_wsweep(const BLevel *__restrict__ tab, const int *__restrict__ units, int
   }
 }
 
-// Batched residuals with one wavefront per cell:
-// role 0: Rbar = rhs - R(st) for the problems that continue to a coarser
-// level; role 1: rhs = R(fbar) + RH (eq. (22)); role 2: partial[cell0 + cell]
+// Batched residuals with one wavefront per cell, one kernel per role
+// (each inlines one copy of the cell update, which keeps its registers
+// down): ROLE 0: Rbar = rhs - R(st) for the problems that continue to a
+// coarser level; 1: rhs = R(fbar) + RH (eq. (22)); 2: partial[cell0 + cell]
 // = weighted |rhs - R(st)|^2 ds (eq. (28)).  Every cell is independent: the
-// wavefronts stride over the group's cells.
-template <int M, int ORDER, int WPG>
+// wavefronts stride over the group's cells and look their problem up only
+// when a cell leaves the problem of the previous one.
+template <int M, int ORDER, int WPG, int ROLE>
 __global__ __launch_bounds__(WPG * WAVE) __attribute__((amdgpu_waves_per_eu(WOcc<M>::W)))
 void k_wresidual(const BLevel *__restrict__ tab, int nslot, int ncell,
-                 const int *__restrict__ active, int role, double *partial) {
+                 const int *__restrict__ active, double *partial) {
   __shared__ WSweepLds<M, WPG> sh;
   load_tabs<M>(sh.tabs);
   __syncthreads();
@@ -154,31 +156,37 @@ void k_wresidual(const BLevel *__restrict__ tab, int nslot, int ncell,
   wzero<double, M>(lw, lane);
   WSlot<M> S;
   S.init(lane);
-  int staged = -1;
+  int slot = -1, lo = 0, hi = 0;
+  bool skip = true;
   for (int cell = blockIdx.x * WPG + wv; cell < ncell; cell += gridDim.x * WPG) {
-    const int slot = find_slot(tab, nslot, cell);
-    const BLevel &B = tab[slot];
-    if (!active[B.inst] || (role == 0 && !B.cont)) continue;
-    if (slot != staged) {
-      constexpr int n32 = (int)(sizeof(LevelArgs) / sizeof(uint32_t));
-      const uint32_t *src = reinterpret_cast<const uint32_t *>(&B.A);
-      uint32_t *dst = reinterpret_cast<uint32_t *>(&A);
-      wsync();
-      for (int x = lane; x < n32; x += WAVE) dst[x] = src[x];
-      wsync();
-      staged = slot;
+    if (cell < lo || cell >= hi) {
+      slot = uni(find_slot(tab, nslot, cell));
+      const BLevel &B = tab[slot];
+      lo = uni(B.cell0);
+      hi = lo + uni(B.ncell);
+      skip = !active[B.inst] || (ROLE == 0 && !B.cont);
+      if (!skip) {
+        constexpr int n32 = (int)(sizeof(LevelArgs) / sizeof(uint32_t));
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(&B.A);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(&A);
+        wsync();
+        for (int x = lane; x < n32; x += WAVE) dst[x] = src[x];
+        wsync();
+      }
     }
-    const int c = cell - B.cell0;
+    if (skip) continue;
+    const BLevel &B = tab[slot];
+    const int c = cell - lo;
     const int i = c % A.nx, j = c / A.nx;
-    if (role == 1)
+    if constexpr (ROLE == 1)
       wave_cell<double, M, ORDER, MODE_FAS>(A, lw, sh.tabs, S, lane, B.fbar, nullptr, i, j, nullptr,
                                             B.RH, B.rhs, nullptr);
-    else if (role == 0)
+    else if constexpr (ROLE == 0)
       wave_cell<double, M, ORDER, MODE_DEFECT>(A, lw, sh.tabs, S, lane, B.st, B.rhs, i, j, nullptr,
                                                nullptr, B.Rbar, nullptr);
     else
       wave_cell<double, M, ORDER, MODE_DEFECT>(A, lw, sh.tabs, S, lane, B.st, B.rhs, i, j, nullptr,
-                                               nullptr, nullptr, partial + B.cell0);
+                                               nullptr, nullptr, partial + lo);
   }
 }
 
@@ -212,17 +220,17 @@ void k_wres1(LevelArgs A, const double *__restrict__ st, const double *__restric
                                       cell % A.nx, cell / A.nx, nullptr, Radd, out, norm_part);
 }
 
-template <int M, int ORDER>
+template <int M, int ORDER, int ROLE>
 int wresidual_occupancy() {
-  int per = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_wresidual<M, ORDER, Wpg<M>::W>, Wpg<M>::W * WAVE,
-                                                   0) != hipSuccess)
-    return 0;
+  static int per = -1;  // per (M, ORDER, ROLE); the device's CU layout is fixed
+  if (per < 0) {
+    int p = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, k_wresidual<M, ORDER, Wpg<M>::W, ROLE>,
+                                                     Wpg<M>::W * WAVE, 0) != hipSuccess)
+      return 0;
+    per = p;
+  }
   return per;
-}
-template <int M>
-int wresidual_per_cu(int order) {
-  return order == 1 ? wresidual_occupancy<M, 1>() : wresidual_occupancy<M, 2>();
 }
 
 template <int M, int ORDER>
@@ -255,6 +263,31 @@ hipError_t launch_wsweep(int M, int order, int grid, const BLevel *tab, const in
   return hipGetLastError();
 }
 
+template <int M, int ORDER, int ROLE>
+static void wresidual_launch_r(int ncell, const BLevel *tab, int nslot, const int *active,
+                               double *partial, int ncu, hipStream_t s) {
+  constexpr int W = Wpg<M>::W;
+  const int per = wresidual_occupancy<M, ORDER, ROLE>();
+  const int need = (ncell + W - 1) / W;
+  const int grid = std::max(1, std::min(need, std::max(per, 1) * ncu));
+  hipLaunchKernelGGL((k_wresidual<M, ORDER, W, ROLE>), dim3(grid), dim3(W * WAVE), 0, s, tab, nslot,
+                     ncell, active, partial);
+}
+
+template <int M>
+static void wresidual_launch(int order, int role, int ncell, const BLevel *tab, int nslot,
+                             const int *active, double *partial, int ncu, hipStream_t s) {
+  if (order == 1) {
+    if (role == 0) wresidual_launch_r<M, 1, 0>(ncell, tab, nslot, active, partial, ncu, s);
+    else if (role == 1) wresidual_launch_r<M, 1, 1>(ncell, tab, nslot, active, partial, ncu, s);
+    else wresidual_launch_r<M, 1, 2>(ncell, tab, nslot, active, partial, ncu, s);
+  } else {
+    if (role == 0) wresidual_launch_r<M, 2, 0>(ncell, tab, nslot, active, partial, ncu, s);
+    else if (role == 1) wresidual_launch_r<M, 2, 1>(ncell, tab, nslot, active, partial, ncu, s);
+    else wresidual_launch_r<M, 2, 2>(ncell, tab, nslot, active, partial, ncu, s);
+  }
+}
+
 hipError_t launch_wresidual(int M, int order, int ncell, const BLevel *tab, int nslot,
                             const int *active, int role, double *partial, hipStream_t s) {
   if (ncell <= 0) return hipSuccess;
@@ -263,18 +296,8 @@ hipError_t launch_wresidual(int M, int order, int ncell, const BLevel *tab, int 
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return hipErrorInvalidDevice;
-  NRXX_DISPATCH_MW(M, {
-    const int per = wresidual_per_cu<MM>(order);
-    constexpr int W = Wpg<MM>::W;
-    const int need = (ncell + W - 1) / W;
-    const int grid = std::max(1, std::min(need, std::max(per, 1) * ncu));
-    if (order == 1)
-      hipLaunchKernelGGL((k_wresidual<MM, 1, W>), dim3(grid), dim3(W * WAVE), 0, s, tab, nslot,
-                         ncell, active, role, partial);
-    else
-      hipLaunchKernelGGL((k_wresidual<MM, 2, W>), dim3(grid), dim3(W * WAVE), 0, s, tab, nslot,
-                         ncell, active, role, partial);
-  });
+  if (role < 0 || role > 2) return hipErrorInvalidValue;
+  NRXX_DISPATCH_MW(M, { wresidual_launch<MM>(order, role, ncell, tab, nslot, active, partial, ncu, s); });
   return hipGetLastError();
 }
 
