@@ -631,6 +631,10 @@ __device__ void wave_cell(const LevelArgs &A, Real *lw, const WTabs<M> &T, const
   // parameters of the cell's own face states (E, W, N, S), kept for the
   // in-cell regularisation
   Real *op = lw + L::OP;
+  // the stencil records of the face direction at hand (+1, -1, +2, -2
+  // along it), read together at the direction's first face: one memory
+  // round trip per direction when they are not gathered
+  Cell<Real, M> P1, M1, P2, M2;
   // faces E, W, N, S in turn (a run-time loop: one copy of the face code)
 #pragma unroll 1
   for (int f = 0; f < 4; ++f) {
@@ -641,15 +645,27 @@ __device__ void wave_cell(const LevelArgs &A, Real *lw, const WTabs<M> &T, const
     const int sd = (f & 1) ? -1 : 1;
     const Real side = (Real)sd;
     const bool flat = ORDER == 1 || k == 0 || k == n - 1;
+    // (gathered records are read from LDS where used instead)
+    if (!L::GATHER && (f & 1) == 0) {
+      // only records inside the grid (the uses below stay within them)
+      if (k + 1 < n) cell_q<Real, M>(A, st, rr, i, j, lw, q_of(D, 1), S, lane, P1);
+      if (k >= 1) cell_q<Real, M>(A, st, rr, i, j, lw, q_of(D, -1), S, lane, M1);
+      if (ORDER == 2 && k + 2 < n) cell_q<Real, M>(A, st, rr, i, j, lw, q_of(D, 2), S, lane, P2);
+      if (ORDER == 2 && k >= 2) cell_q<Real, M>(A, st, rr, i, j, lw, q_of(D, -2), S, lane, M2);
+    }
 
-    // own face state
+    // own face state (not flat: 1 <= k <= n - 2, so P1 and M1 are inside)
     Cell<Real, M> Xo;
     if (flat) Xo = c;
     else {
-      Cell<Real, M> hi, lo;
-      cell_q<Real, M>(A, st, rr, i, j, lw, q_of(D, 1), S, lane, hi);
-      cell_q<Real, M>(A, st, rr, i, j, lw, q_of(D, -1), S, lane, lo);
-      face_state<Real, M>(c, hi, lo, A.limiter, false, side, Xo);
+      if constexpr (L::GATHER) {
+        Cell<Real, M> hi, lo;
+        cell_q<Real, M>(A, st, rr, i, j, lw, q_of(D, 1), S, lane, hi);
+        cell_q<Real, M>(A, st, rr, i, j, lw, q_of(D, -1), S, lane, lo);
+        face_state<Real, M>(c, hi, lo, A.limiter, false, side, Xo);
+      } else {
+        face_state<Real, M>(c, P1, M1, A.limiter, false, side, Xo);
+      }
       Xo.u1 = uni(Xo.u1);
       Xo.u2 = uni(Xo.u2);
       Xo.th = uni(Xo.th);
@@ -677,12 +693,15 @@ __device__ void wave_cell(const LevelArgs &A, Real *lw, const WTabs<M> &T, const
       const bool nflat = ORDER == 1 || kn == 0 || kn == n - 1;
       Cell<Real, M> Xn;
       {
-        Cell<Real, M> nb;
-        cell_q<Real, M>(A, st, rr, i, j, lw, q_of(D, sd), S, lane, nb);
+        // the neighbour (inside the grid) and, not flat (1 <= kn <= n - 2),
+        // the one beyond it
+        Cell<Real, M> nb, far;
+        if constexpr (L::GATHER) cell_q<Real, M>(A, st, rr, i, j, lw, q_of(D, sd), S, lane, nb);
+        else nb = sd > 0 ? P1 : M1;
         if (nflat) Xn = nb;
         else {
-          Cell<Real, M> far;
-          cell_q<Real, M>(A, st, rr, i, j, lw, q_of(D, 2 * sd), S, lane, far);
+          if constexpr (L::GATHER) cell_q<Real, M>(A, st, rr, i, j, lw, q_of(D, 2 * sd), S, lane, far);
+          else far = sd > 0 ? P2 : M2;
           if (sd > 0) face_state<Real, M>(nb, far, c, A.limiter, false, -side, Xn);
           else face_state<Real, M>(nb, c, far, A.limiter, false, -side, Xn);
           Xn.u1 = uni(Xn.u1);
