@@ -1,14 +1,16 @@
 // nrxx_mlp.hip -- the warm-start network on gfx950: a stack of affine
 // layers with SiLU activations between them, trained with Adam on a mean
 // squared error, all in hand-written kernels.  Matrix products run on the
-// matrix cores (v_mfma_f32_16x16x16_bf16: BF16 operands, FP32 accumulation);
+// matrix cores (gfx950's v_mfma_f32_16x16x32_bf16, and 16x16x16 for a last
+// block of 16 in k: BF16 operands, FP32 accumulation);
 // weights have an FP32 master copy and BF16 working copies (row-major and
 // transposed); activations are kept in FP32 (pre-activations) and BF16
 // (row-major and transposed, the MFMA operands).
 //
 // Every product is C[m][n] = sum_k A[m][k] B[n][k] with both operands
-// row-major along k, so every MFMA operand fragment (4 consecutive k of one
-// row) is one 8-byte load:
+// row-major along k, so every MFMA operand fragment (8 consecutive k of one
+// row, or 4 in a last block of 16) is one 16-byte (8-byte) load; lane l takes
+// row l % 16 of A and of B and the same k of both, so the sum pairs equal k:
 //   forward  layer l: A = a_l (rows x in), B = W_l (out x in)
 //   backward dA:      A = dz_l (rows x out), B = W_l^T (in x out)
 //   backward dW:      A = dz_l^T (out x rows), B = a_l^T (in x rows), the rows
@@ -32,6 +34,7 @@ namespace {
 
 typedef uint16_t bf16;
 typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 constexpr int WAVE = 64;
@@ -64,7 +67,8 @@ struct Epi {
 
 // One workgroup = 4 wavefronts; wavefront w computes rows
 // (blockIdx.x * 4 + w) * 16 .. + 15 and WN column tiles of 16 starting at
-// blockIdx.y * 16 * WN; k runs over [kbeg, kbeg + klen), klen % 16 == 0.
+// blockIdx.y * 16 * WN; k runs over [kbeg, kbeg + klen), klen % 16 == 0,
+// in blocks of 32 (16x16x32 MFMA) and a last block of 16 when klen % 32 = 16.
 template <int WN, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(const bf16 *__restrict__ A, int lda,
                                               const bf16 *__restrict__ B, int ldb, int Mrows,
@@ -77,20 +81,30 @@ __global__ __launch_bounds__(256) void k_gemm(const bf16 *__restrict__ A, int ld
   float4_t acc[WN];
 #pragma unroll
   for (int t = 0; t < WN; ++t) acc[t] = float4_t{0.f, 0.f, 0.f, 0.f};
-  const bf16 *ap = A + (size_t)(m0 + r) * lda + kbeg + 4 * q;
+  const bf16 *ap = A + (size_t)(m0 + r) * lda + kbeg;
   const bf16 *bp[WN];
   bool ok[WN];
 #pragma unroll
   for (int t = 0; t < WN; ++t) {
     ok[t] = n0 + 16 * t < Ncols;
-    bp[t] = B + (size_t)(ok[t] ? n0 + 16 * t + r : 0) * ldb + kbeg + 4 * q;
+    bp[t] = B + (size_t)(ok[t] ? n0 + 16 * t + r : 0) * ldb + kbeg;
   }
-  for (int k = 0; k < klen; k += 16) {
-    const short4_t a = *(const short4_t *)(ap + k);
+  const int k32 = klen - klen % 32;
+  for (int k = 0; k < k32; k += 32) {
+    const bf16x8_t a = *(const bf16x8_t *)(ap + k + 8 * q);
 #pragma unroll
     for (int t = 0; t < WN; ++t)
       if (ok[t]) {
-        const short4_t b = *(const short4_t *)(bp[t] + k);
+        const bf16x8_t b = *(const bf16x8_t *)(bp[t] + k + 8 * q);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+      }
+  }
+  if (k32 < klen) {
+    const short4_t a = *(const short4_t *)(ap + k32 + 4 * q);
+#pragma unroll
+    for (int t = 0; t < WN; ++t)
+      if (ok[t]) {
+        const short4_t b = *(const short4_t *)(bp[t] + k32 + 4 * q);
         acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
       }
   }
