@@ -166,6 +166,30 @@ def test_batch_vcycle_bitwise_equals_single_problem_vcycles(levels, kernel):
     assert np.array_equal(got_norms, np.array(want_norms))
 
 
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_batch_w_cycle_bitwise_equals_single_problem_w_cycles(kernel):
+    # gamma = 2 (two coarse-grid corrections per level, Alg. 2) on problems
+    # of different level counts, both sweep kernels
+    require_gpu()
+    from paper_2206_13164_amd import nrxx as N
+    specs = [dict(s, gamma=2) for s in mixed_specs((3, 3, 2, 1, 3))]
+    b = N.Batch(specs)
+    for g in range(b.groups()):
+        t = b.tuning(g)
+        b.set_tuning(g, t["team_width"], t["grid"], t["unit_order"], t["split"], kernel=kernel)
+    st = [x.clone() for x in random_states(b, specs, 43)]
+    want_norms = []
+
+    def one(ctx, d):
+        want_norms.append(ctx.fas_vcycle(d))
+
+    want = single_results(specs, st, one)
+    got_norms = b.vcycle(st)
+    for k in range(len(specs)):
+        assert bool((st[k] == want[k]).all()), k
+    assert np.array_equal(got_norms, np.array(want_norms))
+
+
 def test_batch_solve_masks_graph_replays_and_cycle_counts():
     require_gpu()
     from paper_2206_13164_amd import nrxx as N
