@@ -16,6 +16,7 @@
 // price of a downstream column starting kb rows later.  Results are
 // bit-identical to the cell-team kernels for every kb.
 #include <algorithm>
+#include <atomic>
 
 #include "nrxx_wave.hpp"
 
@@ -222,15 +223,19 @@ void k_wres1(LevelArgs A, const double *__restrict__ st, const double *__restric
 
 template <int M, int ORDER, int ROLE>
 int wresidual_occupancy() {
-  static int per = -1;  // per (M, ORDER, ROLE); the device's CU layout is fixed
-  if (per < 0) {
+  // workgroups per CU of this instance: a property of the kernel and the
+  // architecture, asked once (threads racing here store the same value)
+  static std::atomic<int> per{-1};
+  int v = per.load(std::memory_order_relaxed);
+  if (v < 0) {
     int p = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, k_wresidual<M, ORDER, Wpg<M>::W, ROLE>,
                                                      Wpg<M>::W * WAVE, 0) != hipSuccess)
       return 0;
-    per = p;
+    per.store(p, std::memory_order_relaxed);
+    v = p;
   }
-  return per;
+  return v;
 }
 
 template <int M, int ORDER>
