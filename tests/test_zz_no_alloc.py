@@ -16,7 +16,7 @@ def _spec(nx, ny, M, order):
                   wall_theta=[1.4, 1.0, 1.0, 0.9])
 
 
-@pytest.mark.parametrize("M,order", [(5, 2), (3, 1)])
+@pytest.mark.parametrize("M,order", [(5, 2), (3, 1), (10, 2)])
 def test_noalloc_residual_equals_context_residual(M, order):
     torch = require_gpu()
     from paper_2206_13164_amd import nrxx as N
