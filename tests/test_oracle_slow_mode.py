@@ -1,0 +1,72 @@
+"""Oracle (CPU): the slowest mode of the single-level iterations on the
+single lid-driven cavity, which sets their iteration counts (Sec. 4,
+Tables 1 and 2, Euler and FS columns).
+
+On the single lid the forward-Euler and fast-sweeping counts are about 1.2x
+the paper's while the four-sided cavity's (Table 6) match.  At equal Kn and
+grid the two setups differ only in the wall velocities, and their late-time
+Euler increments show where the difference lives: the single lid's slowest
+mode is a flow along x, nearly uniform across y (tangential to the bottom
+and top walls), with a density and temperature dipole along x.  It is odd
+under the 180-degree rotation the four-sided setup is invariant to, so the
+four-sided cavity never excites it and converges at the rate of a faster
+mode.  With nearly no shear across y in the interior, this mode loses its
+momentum mainly to the bottom and top walls, so its decay rate -- and with
+it the single-lid counts -- depends on the wall flux, whose details the
+paper leaves to its references."""
+import numpy as np
+
+import oracle as orc
+from paper_2206_13164_amd import inputs as I
+from paper_2206_13164_amd import paper_tables as T
+
+STEPS, EVERY = 600, 50
+
+
+def late_euler(wall_u, n=16, kn=0.777, height=1, steps=STEPS):
+    """Log-residual decay per step over the second half of `steps` forward
+    Euler steps from the Maxwellian, and the last step's increment; the
+    cavity is `height` times as tall as wide, at the same cell size."""
+    s = T.row_spec(dict(Kn=kn, nx=n, wall_u=wall_u, levels=1))
+    s = dict(s, ny=n * height, ly=float(height))
+    P = orc.problem(s)
+    st = I.maxwellian_state(s, 0)
+    hist = []
+    for k in range(steps):
+        orc.euler_step(P, st)
+        if k % EVERY == EVERY - 1:
+            hist.append(orc.residual(P, 0, st)[1])
+    before = st.copy()
+    orc.euler_step(P, st)
+    h = np.log(hist)
+    half = len(h) // 2
+    rate = (h[-1] - h[half]) / (EVERY * (len(h) - 1 - half))  # log-residual per step
+    return rate, st - before
+
+
+def rotation_parts(u):
+    """(symmetric, symmetry-breaking) norms of a velocity component under the
+    180-degree rotation, which maps u(x) to -u(-x)."""
+    rot = -u[::-1, ::-1]
+    return np.linalg.norm(u + rot) / 2, np.linalg.norm(u - rot) / 2
+
+
+def test_single_lid_slow_mode_is_rotation_odd_and_decays_slower_than_the_four_sided():
+    r1, d1 = late_euler([0.0, 0.0, T.U_W, 0.0])            # single lid
+    r4, d4 = late_euler([-T.U_W, T.U_W, T.U_W, -T.U_W])    # four-sided, anti-parallel
+    sym4, brk4 = rotation_parts(d4[:, :, 0])
+    sym1, brk1 = rotation_parts(d1[:, :, 0])
+    assert brk4 <= 1e-4 * sym4      # the four-sided iteration keeps the symmetry
+    assert sym1 <= 0.05 * brk1      # the single lid's slow mode breaks it
+    # x-velocity of the mode: nearly the same profile in every interior row
+    u1 = d1[:, :, 0] / np.abs(d1[:, :, 0]).max()
+    rows = u1[2:-2]
+    assert np.abs(rows - rows.mean(axis=0)).max() < 0.2
+    # it decays markedly slower than anything the four-sided cavity excites
+    assert r1 < 0 and r4 < 0
+    assert r1 > 0.9 * r4
+    # twice as tall a cavity (same cells, so the same Euler step): the mode
+    # decays about half as fast, as it would if the bottom and top walls,
+    # not the interior, took most of its momentum
+    r2, _ = late_euler([0.0, 0.0, T.U_W, 0.0], height=2, steps=1000)
+    assert 0.35 < r2 / r1 < 0.65
