@@ -48,10 +48,9 @@ def test_m10_nmg_iterations_match_the_paper(table, kn):
 # the paper's at every grid and Kn, and the NMG count at 256x256, Kn 1.0 is
 # 38 against 27; the four-sided and bottom-heated rows of the same code match.
 # The single lid's slowest single-level mode, which the symmetric setups do
-# not excite, decays through the bottom and top walls' tangential momentum
-# flux (tests/test_oracle_slow_mode.py), so the gap points at the wall
-# condition the paper takes from its references; these tests track it.
-@pytest.mark.xfail(reason="single-lid FS count 279 vs the paper's 231 (1.21x): the wall condition damps the single lid's slow mode less",
+# not excite, decays slower here than the paper's counts imply
+# (tests/test_oracle_slow_mode.py); the cause is open and these tests track it.
+@pytest.mark.xfail(reason="single-lid FS count 279 vs the paper's 231 (1.21x): the single lid's slow mode decays slower",
                    strict=True)
 def test_single_lid_fast_sweeping_iterations_match_the_paper():
     require_gpu()
@@ -61,7 +60,7 @@ def test_single_lid_fast_sweeping_iterations_match_the_paper():
     assert abs(fs["iterations"] - paper[1]) <= 0.05 * paper[1]
 
 
-@pytest.mark.xfail(reason="single-lid Euler count 2205 vs the paper's 1823 (1.21x): the wall condition damps the single lid's slow mode less",
+@pytest.mark.xfail(reason="single-lid Euler count 2205 vs the paper's 1823 (1.21x): the single lid's slow mode decays slower",
                    strict=True)
 def test_single_lid_euler_iterations_match_the_paper():
     require_gpu()

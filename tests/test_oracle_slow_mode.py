@@ -10,10 +10,9 @@ mode is a flow along x, nearly uniform across y (tangential to the bottom
 and top walls), with a density and temperature dipole along x.  It is odd
 under the 180-degree rotation the four-sided setup is invariant to, so the
 four-sided cavity never excites it and converges at the rate of a faster
-mode.  With nearly no shear across y in the interior, this mode loses its
-momentum mainly to the bottom and top walls, so its decay rate -- and with
-it the single-lid counts -- depends on the wall flux, whose details the
-paper leaves to its references."""
+mode.  The paper's counts imply that its iterations damp this motion
+faster; here the global Euler step is the same in both setups and both
+residual tails start from the same fraction of the initial residual."""
 import numpy as np
 
 import oracle as orc
@@ -23,12 +22,10 @@ from paper_2206_13164_amd import paper_tables as T
 STEPS, EVERY = 600, 50
 
 
-def late_euler(wall_u, n=16, kn=0.777, height=1, steps=STEPS):
+def late_euler(wall_u, n=16, kn=0.777, steps=STEPS):
     """Log-residual decay per step over the second half of `steps` forward
-    Euler steps from the Maxwellian, and the last step's increment; the
-    cavity is `height` times as tall as wide, at the same cell size."""
+    Euler steps from the Maxwellian, and the last step's increment."""
     s = T.row_spec(dict(Kn=kn, nx=n, wall_u=wall_u, levels=1))
-    s = dict(s, ny=n * height, ly=float(height))
     P = orc.problem(s)
     st = I.maxwellian_state(s, 0)
     hist = []
@@ -65,8 +62,3 @@ def test_single_lid_slow_mode_is_rotation_odd_and_decays_slower_than_the_four_si
     # it decays markedly slower than anything the four-sided cavity excites
     assert r1 < 0 and r4 < 0
     assert r1 > 0.9 * r4
-    # twice as tall a cavity (same cells, so the same Euler step): the mode
-    # decays about half as fast, as it would if the bottom and top walls,
-    # not the interior, took most of its momentum
-    r2, _ = late_euler([0.0, 0.0, T.U_W, 0.0], height=2, steps=1000)
-    assert 0.35 < r2 / r1 < 0.65
