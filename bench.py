@@ -336,9 +336,11 @@ def state_err(a, b, M):
     return float(max(eu, et, ef))
 
 
-def solve_timed(spec, tol, max_cycles, ref=None):
+def solve_timed(spec, tol, max_cycles, ref=None, label=None):
     """One warm-up cycle, then a timed solve from the Maxwellian; returns the
-    record, the final host state and the context's sweep statistics."""
+    record, the final host state and the context's sweep statistics.  With a
+    label, the solve's window on the host clock is logged under it (for
+    selecting its dispatches in a kernel trace)."""
     import torch
     from paper_2206_13164_amd import nrxx as N
     ctx = N.Context(spec)
@@ -350,10 +352,13 @@ def solve_timed(spec, tol, max_cycles, ref=None):
     ctx.init_maxwellian(st)
     ctx.sweep_stats(reset=True)
     torch.cuda.synchronize()
+    w0 = time.monotonic_ns()
     t0 = time.perf_counter()
     rc, cyc, hist = ctx.solve(st, tol, max_cycles, ref_norm=ref)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    if label:
+        log(f"{label} window monotonic_ns {w0} {time.monotonic_ns()}")
     sms, scells, slaunch = ctx.sweep_stats(reset=True)
     host = ctx.to_host(st, math.comb(spec["M"] + 3, 3) + 3)
     ctx.close()
@@ -378,8 +383,9 @@ def heated_leg(max_cycles):
     out = {}
     for name in ("heated256_shakhov_m8_kn005", "heated256_shakhov_m8_kn02"):
         s = I.spec(name)
-        p0, h0, ref = solve_timed(s, s["tol"], max_cycles)
-        p1, h1, _ = solve_timed(dict(s, precision=1), s["tol"], max_cycles, ref=ref)
+        p0, h0, ref = solve_timed(s, s["tol"], max_cycles, label=f"{name}_fp64")
+        p1, h1, _ = solve_timed(dict(s, precision=1), s["tol"], max_cycles, ref=ref,
+                                label=f"{name}_fp32_blocks")
         out[name] = {"Kn": s["Kn"], "fp64": p0, "fp32_blocks": p1,
                      "speedup_fp32_blocks": p0["seconds"] / p1["seconds"],
                      "mirror_asymmetry_fp64": state_err(mirror_x(h0, 8), h0, 8),
@@ -421,7 +427,7 @@ def single_leg(workload, max_cycles):
     dependency chain of the sweeps)."""
     from paper_2206_13164_amd import inputs as I
     s = I.spec(workload)
-    rec, _, _ = solve_timed(s, s["tol"], max_cycles)
+    rec, _, _ = solve_timed(s, s["tol"], max_cycles, label=workload)
     NA = math.comb(s["M"] + 3, 3)
     rec["workload"] = workload
     rec["cell_moment_updates_per_s"] = rec["cycles"] * cycle_accounting(s)["cells"] * NA / rec["seconds"]

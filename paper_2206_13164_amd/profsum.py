@@ -15,7 +15,10 @@ any kernel ran.
 
 The second form sums each counter over its hardware instances per dispatch
 (``--pmc`` runs) and prints the per-dispatch average per kernel, over the
-timed window when the bench's stderr is given.
+timed window when the bench's stderr is given.  The single-problem legs log
+their solves as ``<label> window monotonic_ns <start> <end>`` (label = the
+workload, plus ``_fp64`` / ``_fp32_blocks`` on the heated cavity);
+``--window LABEL`` selects one of those instead of the headline's.
 """
 from __future__ import annotations
 
@@ -25,10 +28,11 @@ import re
 import sqlite3
 
 
-def window(stderr_text: str):
-    m = re.search(r"timed window monotonic_ns (\d+) (\d+)", stderr_text)
+def window(stderr_text: str, label: str = "timed"):
+    """Host-clock window the bench logged as '<label> window monotonic_ns a b'."""
+    m = re.search(re.escape(label) + r" window monotonic_ns (\d+) (\d+)", stderr_text)
     if not m:
-        raise SystemExit("no timed window line in the bench output")
+        raise SystemExit(f"no '{label} window' line in the bench output")
     return int(m.group(1)), int(m.group(2))
 
 
@@ -84,9 +88,11 @@ def main():
     ap.add_argument("mode", choices=["trace", "counters"])
     ap.add_argument("db")
     ap.add_argument("bench_stderr", nargs="?")
+    ap.add_argument("--window", default="timed",
+                    help="label of the logged window (default: the headline's timed window)")
     args = ap.parse_args()
     if args.mode == "counters":
-        w = window(open(args.bench_stderr).read()) if args.bench_stderr else (None, None)
+        w = window(open(args.bench_stderr).read(), args.window) if args.bench_stderr else (None, None)
         res = counters(args.db, *w)
         names = sorted({c for d in res.values() for c in d})
         print("| kernel | dispatches | " + " | ".join(names) + " |")
@@ -97,10 +103,10 @@ def main():
         return
     if not args.bench_stderr:
         raise SystemExit("trace mode needs the bench's stderr")
-    w0, w1 = window(open(args.bench_stderr).read())
+    w0, w1 = window(open(args.bench_stderr).read(), args.window)
     per, busy = summarise(args.db, w0, w1)
     W = w1 - w0
-    print(f"timed window {W / 1e6:.1f} ms; some kernel running {busy / 1e6:.1f} ms "
+    print(f"{args.window} window {W / 1e6:.1f} ms; some kernel running {busy / 1e6:.1f} ms "
           f"({100.0 * busy / max(W, 1):.0f} %)")
     print(f"| kernel | calls | total ms | avg us | workgroups x threads, VGPRs, LDS B, scratch B |")
     print("|---|---:|---:|---:|---|")

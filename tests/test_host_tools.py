@@ -100,3 +100,14 @@ def test_warm_start_gate_and_validation_draws():
     for a, b in zip(v, train):  # the training stream's draws 2000.. at 256^2, M = 5
         assert a["Kn"] == b["Kn"] and a["wall_u"] == b["wall_u"]
         assert (a["nx"], a["ny"], a["M"], a["levels"], a["tol"]) == (256, 256, 5, 6, 1e-8)
+
+
+def test_profsum_selects_a_labelled_window():
+    text = ("[bench] timed window monotonic_ns 1 2 boottime_ns 3 4\n"
+            "[bench] heated256_shakhov_m8_kn005_fp64 window monotonic_ns 10 20\n"
+            "[bench] heated256_shakhov_m8_kn005_fp32_blocks window monotonic_ns 30 40\n")
+    assert P.window(text) == (1, 2)
+    assert P.window(text, "heated256_shakhov_m8_kn005_fp64") == (10, 20)
+    assert P.window(text, "heated256_shakhov_m8_kn005_fp32_blocks") == (30, 40)
+    with pytest.raises(SystemExit):
+        P.window(text, "heated256_shakhov_m8_kn02_fp64")
