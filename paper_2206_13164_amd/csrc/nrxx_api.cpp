@@ -566,7 +566,10 @@ int nrxx_create(const nrxx_problem *p, void *hip_stream, nrxx_ctx **out) {
   // sweeps (automatic or 3), static persistent (one workgroup per column,
   // all resident at once; 2) or one launch per anti-diagonal (1)
   if (P.schedule == 0 || P.schedule == 3) {
-    c->qnw = P.M <= 5 ? 8 : 2;
+    // wavefronts per cell team: one problem keeps few cells in flight, so
+    // wider teams (shorter cell updates) win; at M >= 6 a team of eight
+    // does not fit the LDS, and four beat two on the 256^2 M = 8 solves
+    c->qnw = P.M <= 5 ? 8 : 4;
     c->qgrid = P.M > MTEAM ? wsweep_resident(P.M, P.order) : bsweep_resident(P.M, P.order, c->qnw, 1);
     c->qgrid32 = P.precision == 1 ? bsweep_resident32(P.M, P.order, c->qnw) : 1;
     bool qok = c->qgrid >= 1 && c->qgrid32 >= 1 &&
