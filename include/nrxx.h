@@ -304,7 +304,12 @@ int nrxx_batch_set_tuning(nrxx_batch *b, int group, const nrxx_batch_tuning *t);
  * resident, half} x unit order; wavefront-per-cell kernel with rows_per_sync 1:
  * grid x unit order)
  * on one s1-step smoothing block of the finest level of `states`, keeps the
- * fastest per group, and restores `states` bit for bit. */
+ * fastest per group; then, with two or more groups (which run at once and
+ * share the device), times one NMG iteration of all groups at once for each
+ * combination of per-group grids of 1, 3/4, 1/2 and 1/4 times the group's
+ * choice (up to 64 combinations, else one group at a time) and keeps the
+ * fastest if, timed again, it beats the groups' own grids by at least 1.5 %.
+ * Restores `states` bit for bit. */
 int nrxx_batch_autotune(nrxx_batch *b, double *const *states);
 /* Global Maxwellian in every problem. */
 int nrxx_batch_init_maxwellian(nrxx_batch *b, double *const *states, double rho, double u1,

@@ -334,6 +334,109 @@ int set_all_active(nrxx_batch *b, int v) {
   return NRXX_OK;
 }
 
+// Joint step of the autotuner.  The groups' persistent sweeps run at once
+// and share the CUs, so the grid each group chose alone can crowd the other
+// groups' sweeps and light kernels out, and the best shares depend on each
+// other (one group's smaller grid pays off only with another's).  Every
+// combination of per-group grids of 1, 3/4, 1/2 and 1/4 times the group's
+// own choice (at most SHARE_MAX_COMBOS combinations, else each group in
+// turn) is timed as one whole NMG iteration (V-cycle, mass fix, norms) of
+// all groups at once from the same states; the fastest is timed once more
+// against the groups' own grids and kept only when it is still at least
+// SHARE_GAIN faster.  Every problem's finest-level state is restored
+// afterwards (coarse levels are rebuilt by restriction in every cycle).
+constexpr double SHARE_GAIN = 0.015;
+constexpr int SHARE_MAX_COMBOS = 64;
+
+int tune_shares(nrxx_batch *b, double *const *states, hipEvent_t t0, hipEvent_t t1) {
+  std::vector<double *> bak(b->n, nullptr);
+  std::vector<size_t> nbytes(b->n, 0);
+  bool ok = true;
+  for (auto &G : b->g)
+    for (size_t s = 0; s < G.inst.size() && ok; ++s) {
+      const int i = G.inst[s];
+      nbytes[i] = (size_t)G.htab[0][s].ncell * G.stride * sizeof(double);
+      ok = hipMalloc((void **)&bak[i], nbytes[i]) == hipSuccess &&
+           hipMemcpyAsync(bak[i], states[i], nbytes[i], hipMemcpyDeviceToDevice, b->stream) == hipSuccess;
+    }
+  auto release = [&]() {
+    for (double *p : bak)
+      if (p) (void)hipFree(p);
+  };
+  auto restore = [&]() {
+    for (int i = 0; i < b->n; ++i)
+      if (hipMemcpyAsync(states[i], bak[i], nbytes[i], hipMemcpyDeviceToDevice, b->stream) != hipSuccess)
+        return false;
+    return hipStreamSynchronize(b->stream) == hipSuccess;
+  };
+  // one concurrent NMG iteration from the backed-up states, in ms
+  auto cycle_ms = [&](float *ms) -> int {
+    if (!restore()) return bfail(b, NRXX_EHIP, "autotune: copy failed");
+    BCHK(hipEventRecord(t0, b->stream));
+    int rc = on_groups(b, [&](Group &G) { return cycle_enqueue(b, G, false); });
+    if (rc) return rc;
+    BCHK(hipEventRecord(t1, b->stream));
+    BCHK(hipEventSynchronize(t1));
+    BCHK(hipEventElapsedTime(ms, t0, t1));
+    return fetch(b);
+  };
+  if (!ok) {
+    release();
+    return bfail(b, NRXX_EHIP, "autotune: copy or allocation failed");
+  }
+  const int ng = (int)b->g.size();
+  const int eighths[4] = {8, 6, 4, 2};
+  std::vector<int> own;
+  for (auto &G : b->g) own.push_back(G.grid);
+  auto set_grids = [&](const std::vector<int> &pick) {
+    for (int gi = 0; gi < ng; ++gi) b->g[gi].grid = std::max(1, own[gi] * eighths[pick[gi]] / 8);
+  };
+  // candidate combinations (indices into eighths), the own grids first
+  std::vector<std::vector<int>> combos;
+  int ncombo = 1;
+  for (int gi = 0; gi < ng && ncombo <= SHARE_MAX_COMBOS; ++gi) ncombo *= 4;
+  if (ncombo <= SHARE_MAX_COMBOS) {
+    for (int c = 0; c < ncombo; ++c) {
+      std::vector<int> pick(ng);
+      for (int gi = 0, x = c; gi < ng; ++gi, x /= 4) pick[gi] = x % 4;
+      combos.push_back(pick);
+    }
+  } else {
+    combos.push_back(std::vector<int>(ng, 0));
+    for (int gi = 0; gi < ng; ++gi)
+      for (int e = 1; e < 4; ++e) {
+        std::vector<int> pick(ng, 0);
+        pick[gi] = e;
+        combos.push_back(pick);
+      }
+  }
+  float ms = 0.f, base = 0.f, best = 1e30f;
+  size_t bi = 0;
+  int rc = cycle_ms(&ms);  // loads the light kernels' code objects
+  for (size_t c = 0; c < combos.size() && !rc; ++c) {
+    set_grids(combos[c]);
+    rc = cycle_ms(&ms);
+    if (!rc && ms < best) {
+      best = ms;
+      bi = c;
+    }
+  }
+  if (!rc && bi != 0) {  // confirm against the own grids, timed again
+    set_grids(combos[0]);
+    rc = cycle_ms(&base);
+    if (!rc) {
+      set_grids(combos[bi]);
+      rc = cycle_ms(&best);
+    }
+    if (!rc && !(best < base * (1.0 - SHARE_GAIN))) bi = 0;
+  }
+  set_grids(combos[rc ? 0 : bi]);
+  if (!restore() && !rc) rc = bfail(b, NRXX_EHIP, "autotune: copy failed");
+  release();
+  for (auto &G : b->g) drop_graph(G);
+  return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -782,6 +885,10 @@ int nrxx_batch_autotune(nrxx_batch *b, double *const *states) {
     G.rows = keep.rows;
     G.tuned_ms = best;
     drop_graph(G);
+  }
+  if (b->g.size() >= 2) {
+    rc = tune_shares(b, states, t0, t1);
+    if (rc) return rc;
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
