@@ -307,8 +307,9 @@ int nrxx_batch_set_tuning(nrxx_batch *b, int group, const nrxx_batch_tuning *t);
  * fastest per group; then, with two or more groups (which run at once and
  * share the device), times one NMG iteration of all groups at once for each
  * combination of per-group grids of 1, 3/4, 1/2 and 1/4 times the group's
- * choice (up to 64 combinations, else one group at a time) and keeps the
- * fastest if, timed again, it beats the groups' own grids by at least 1.5 %.
+ * choice (up to 64 combinations, else one group at a time), times the four
+ * fastest three more times interleaved with the own grids, and keeps the
+ * lowest median if it beats the own grids' median by at least 1.5 %.
  * Restores `states` bit for bit. */
 int nrxx_batch_autotune(nrxx_batch *b, double *const *states);
 /* Global Maxwellian in every problem. */

@@ -341,12 +341,16 @@ int set_all_active(nrxx_batch *b, int v) {
 // combination of per-group grids of 1, 3/4, 1/2 and 1/4 times the group's
 // own choice (at most SHARE_MAX_COMBOS combinations, else each group in
 // turn) is timed as one whole NMG iteration (V-cycle, mass fix, norms) of
-// all groups at once from the same states; the fastest is timed once more
-// against the groups' own grids and kept only when it is still at least
-// SHARE_GAIN faster.  Every problem's finest-level state is restored
-// afterwards (coarse levels are rebuilt by restriction in every cycle).
+// all groups at once from the same states; the SHARE_FINALISTS fastest are
+// timed SHARE_REPS times more, interleaved with the groups' own grids (one
+// iteration varies by a few per cent), and the lowest median is kept only
+// when it beats the own grids' median by at least SHARE_GAIN.  Every
+// problem's finest-level state is restored afterwards (coarse levels are
+// rebuilt by restriction in every cycle).
 constexpr double SHARE_GAIN = 0.015;
 constexpr int SHARE_MAX_COMBOS = 64;
+constexpr int SHARE_FINALISTS = 4;
+constexpr int SHARE_REPS = 3;
 
 int tune_shares(nrxx_batch *b, double *const *states, hipEvent_t t0, hipEvent_t t1) {
   std::vector<double *> bak(b->n, nullptr);
@@ -410,25 +414,45 @@ int tune_shares(nrxx_batch *b, double *const *states, hipEvent_t t0, hipEvent_t 
         combos.push_back(pick);
       }
   }
-  float ms = 0.f, base = 0.f, best = 1e30f;
-  size_t bi = 0;
+  // stage 1: one iteration per combination; stage 2: the SHARE_FINALISTS
+  // fastest and the own grids, SHARE_REPS iterations each, interleaved; the
+  // lowest median wins if it beats the own grids' median by SHARE_GAIN
+  float ms = 0.f;
   int rc = cycle_ms(&ms);  // loads the light kernels' code objects
+  std::vector<std::pair<float, size_t>> first;
   for (size_t c = 0; c < combos.size() && !rc; ++c) {
     set_grids(combos[c]);
     rc = cycle_ms(&ms);
-    if (!rc && ms < best) {
-      best = ms;
-      bi = c;
-    }
+    first.push_back({ms, c});
   }
-  if (!rc && bi != 0) {  // confirm against the own grids, timed again
-    set_grids(combos[0]);
-    rc = cycle_ms(&base);
+  size_t bi = 0;
+  if (!rc) {
+    std::sort(first.begin(), first.end());
+    std::vector<size_t> fin{0};
+    for (const auto &f : first)
+      if (f.second != 0 && (int)fin.size() <= SHARE_FINALISTS) fin.push_back(f.second);
+    std::vector<std::vector<float>> t(fin.size());
+    for (int r = 0; r < SHARE_REPS && !rc; ++r)
+      for (size_t k = 0; k < fin.size() && !rc; ++k) {
+        set_grids(combos[fin[k]]);
+        rc = cycle_ms(&ms);
+        t[k].push_back(ms);
+      }
     if (!rc) {
-      set_grids(combos[bi]);
-      rc = cycle_ms(&best);
+      auto median = [](std::vector<float> v) {
+        std::sort(v.begin(), v.end());
+        return v[v.size() / 2];
+      };
+      const float own_ms = median(t[0]);
+      float best = own_ms;
+      for (size_t k = 1; k < fin.size(); ++k) {
+        const float m = median(t[k]);
+        if (m < best && m < own_ms * (1.0 - SHARE_GAIN)) {
+          best = m;
+          bi = fin[k];
+        }
+      }
     }
-    if (!rc && !(best < base * (1.0 - SHARE_GAIN))) bi = 0;
   }
   set_grids(combos[rc ? 0 : bi]);
   if (!restore() && !rc) rc = bfail(b, NRXX_EHIP, "autotune: copy failed");
