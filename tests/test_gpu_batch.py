@@ -285,6 +285,18 @@ def test_batch_autotune_restores_states_and_keeps_results():
     b.sweep(st, nsteps=1)
     for k in range(len(specs)):
         assert bool((st[k] == want[k]).all()), k
+    # whole NMG iterations with the grids the joint (all groups at once)
+    # step settled on
+    want_norms = []
+
+    def one(ctx, d):
+        want_norms.append(ctx.fas_vcycle(d))
+
+    want = single_results(specs, st, one)
+    got_norms = b.vcycle(st)
+    for k in range(len(specs)):
+        assert bool((st[k] == want[k]).all()), k
+    assert np.array_equal(got_norms, np.array(want_norms))
 
 
 @pytest.mark.parametrize("kernel", [0, 1])
